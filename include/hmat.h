@@ -1,0 +1,176 @@
+/*
+ * hmat.h -- C ABI of the MI355X (gfx950) H-matrix-vector product library.
+ *
+ * The library applies an H-matrix under the weak admissibility condition
+ * (Li, Poulson, Ying, "Distributed-memory H-matrix algebra I", Sec. 2):
+ * the matrix is defined by a domain tree (Def. "Domain tree") and by the
+ * blocks that Def. 2.3 produces -- dense blocks D between leaves of one
+ * parent, and low-rank blocks U V^T between distinct siblings at every
+ * non-leaf level. The product is Eq. (2.4), y_t += D_ts x_s and
+ * y_t += U_ts (V_ts^T x_s) over all blocks, in the GEMV form
+ * y = alpha K x + beta y of the remark that closes Sec. 4.1.
+ *
+ * Conventions shared by every entry point:
+ *  - Rows and columns are in tree order: every tree node owns one contiguous
+ *    index range [begin, end). Permuting user vectors into tree order is the
+ *    caller's job.
+ *  - Matrices passed in are FP32, column-major, with a leading dimension.
+ *  - Every call returns an hmat_status; no C++ exception crosses the ABI. On
+ *    failure, hmat_last_error() returns a message for the calling thread.
+ *  - Validation of arguments, tree and blocks happens before any HIP call.
+ */
+#ifndef HMAT_H_
+#define HMAT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hmat_status {
+    HMAT_OK = 0,
+    HMAT_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad leading dimension, unknown handle */
+    HMAT_ERR_BAD_TREE = 2,    /* the tree is not a domain tree (children do not partition the parent) */
+    HMAT_ERR_BAD_BLOCKS = 3,  /* blocks overlap, are missing, or sit on a non-admissible pair */
+    HMAT_ERR_UNSUPPORTED = 4, /* valid input outside what the library implements (see hmat_create) */
+    HMAT_ERR_NOMEM = 5,       /* a device or host allocation failed */
+    HMAT_ERR_DEVICE = 6       /* a HIP call failed (including a fault reported by a later call) */
+} hmat_status;
+
+/* How the factors are stored on the device. Quantisation happens on the host
+ * inside hmat_create; the device only dequantises, exactly. Accumulation is
+ * FP32 in every form. */
+typedef enum hmat_storage {
+    HMAT_STORE_FP32 = 0,          /* D, U, V in FP32 */
+    HMAT_STORE_FP16_SCALED = 1    /* D, U, V in FP16, one power-of-two scale per stored array
+                                     D_ts, U_ts, V_ts: s = 2^(ceil(log2 amax) - 15), q = RNE(v / s) */
+} hmat_storage;
+
+/* Domain tree (Def. "Domain tree", Sec. 2). Node 0 is the root with
+ * parent[0] = -1 and [begin, end) = [0, n). Every other node i has
+ * 0 <= parent[i] < i. The children of a node, taken in increasing node id,
+ * must tile its range contiguously in that order. All leaves must sit at the
+ * same depth. Arrays are host memory, read during hmat_create only. */
+typedef struct hmat_tree_desc {
+    int64_t n;              /* number of points = rows = columns, 1 <= n < 2^31 */
+    int32_t num_nodes;      /* >= 1 */
+    int32_t reserved;       /* must be 0 */
+    const int32_t *parent;  /* [num_nodes] */
+    const int64_t *begin;   /* [num_nodes] */
+    const int64_t *end;     /* [num_nodes] */
+} hmat_tree_desc;
+
+/* One block of Def. 2.3. rank == 0: dense block, a = D_ts (|t| x |s|,
+ * leading dimension lda >= |t|), b unused. rank > 0: low-rank block
+ * K_ts = U V^T with a = U (|t| x rank, lda >= |t|) and b = V (|s| x rank,
+ * ldb >= |s|). FP32 host memory, column-major, read during hmat_create only. */
+typedef struct hmat_block_desc {
+    int32_t target;         /* node id t (rows) */
+    int32_t source;         /* node id s (columns) */
+    int32_t rank;           /* 0 = dense; else 1 <= rank <= min(|t|, |s|) */
+    int32_t reserved;       /* must be 0 */
+    const float *a;
+    int64_t lda;
+    const float *b;
+    int64_t ldb;
+} hmat_block_desc;
+
+typedef struct hmat_options {
+    int32_t storage;        /* hmat_storage */
+    int32_t max_nrhs;       /* largest nrhs hmat_matvec will be called with, >= 1 */
+    int32_t device;         /* HIP device ordinal the data lives on */
+    int32_t flags;          /* must be 0 */
+} hmat_options;
+
+typedef struct hmat_info {
+    int64_t n;
+    int32_t leaf_depth;          /* L: depth of every leaf (root = 0) */
+    int32_t num_chunks;          /* boxes at depth max(L-1, 0): the unit of device work */
+    int64_t num_dense_blocks;
+    int64_t num_lowrank_blocks;
+    int64_t stored_elements;     /* sum |t||s| over dense + (|t|+|s|) r over low-rank blocks */
+    int64_t factor_bytes;        /* bytes of those elements in the storage form, plus scales */
+    int64_t device_factor_bytes; /* bytes the kernels stream, including layout padding */
+    int64_t workspace_bytes;     /* partial sums and z vectors */
+    int32_t storage;
+    int32_t max_nrhs;
+} hmat_info;
+
+typedef struct hmat_handle *hmat_t;
+
+/* Build a device-resident H-matrix from a domain tree and its blocks.
+ *
+ * The block set must be exactly the weak-admissibility structure of Def. 2.3
+ * for the tree: for every node p above the leaves, a low-rank block (t, s)
+ * for each ordered pair of distinct children t != s of p when those children
+ * are not leaves, and a dense block for each ordered pair (t, s) of children
+ * (t == s included) when they are leaves; a root that is itself a leaf takes
+ * one dense block (0, 0). Blocks may come in any order.
+ *
+ * Errors: INVALID_ARG (null pointers, sizes, leading dimensions, ranks,
+ * options); BAD_TREE; BAD_BLOCKS (a block on a recursion pair (c, c) above
+ * the leaves, a duplicate, or a missing pair); UNSUPPORTED (leaves at mixed
+ * depths, blocks between non-siblings as under standard admissibility, a
+ * dense block between non-leaves, a low-rank block between leaves, a chunk
+ * whose vector operand exceeds the kernel's LDS budget); NOMEM; DEVICE.
+ *
+ * Ownership: all inputs are deep-copied and re-laid-out; the handle owns its
+ * device memory until hmat_destroy. On failure *out is set to NULL and
+ * nothing is leaked. The environment variable HMAT_FAULT=alloc makes the
+ * first device allocation fail (NOMEM), for testing the cleanup path. */
+hmat_status hmat_create(const hmat_tree_desc *tree, const hmat_block_desc *blocks,
+                        int64_t num_blocks, const hmat_options *opts, hmat_t *out);
+
+/* y = alpha * K x + beta * y for nrhs right-hand sides.
+ *
+ * x (n x nrhs, leading dimension ldx >= n) and y (n x nrhs, ldy >= n) are
+ * FP32 device pointers on the handle's device, in tree order, owned by the
+ * caller; they must not overlap. When beta == 0, y is not read (NaN in y is
+ * overwritten). 1 <= nrhs <= max_nrhs. The call is asynchronous on `stream`
+ * (a hipStream_t; NULL = the null stream) and does no host synchronisation.
+ * One handle owns one workspace, so calls on the same handle must be ordered
+ * on one stream; distinct handles are independent. The result is
+ * deterministic: the same inputs give bitwise identical y.
+ *
+ * Errors: INVALID_ARG; DEVICE (launch failure). */
+hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx,
+                        float beta, float *y, int64_t ldy, void *stream);
+
+/* Release the handle and its device memory. NULL is a no-op; an unknown or
+ * already destroyed handle gives INVALID_ARG. Work queued on a stream that
+ * still uses the handle must have completed. */
+hmat_status hmat_destroy(hmat_t h);
+
+/* Sizes and counts of a handle (host only, no device call). */
+hmat_status hmat_get_info(hmat_t h, hmat_info *info);
+
+/* Per-phase timing for measurement. While enabled, hmat_matvec records HIP
+ * events around each kernel on the caller's stream; hmat_get_timing waits
+ * for them and returns, per phase, the summed elapsed milliseconds and the
+ * number of calls since timing was enabled. Phases: 0 = V-phase (V^T x
+ * partial sums), 1 = partial reduction and z routing, 2 = U-phase plus dense
+ * near field and output. Enabling resets the sums. */
+#define HMAT_NUM_PHASES 3
+hmat_status hmat_set_timing(hmat_t h, int32_t enable);
+hmat_status hmat_get_timing(hmat_t h, double ms[HMAT_NUM_PHASES], int64_t *calls);
+
+/* HBM bandwidth probe: mode 0 reads `bytes` from src (a multiple of 16 B) and
+ * writes one float per workgroup to dst (dst must hold 65536 floats);
+ * mode 1 copies `bytes` from src to dst. Device pointers, asynchronous on
+ * `stream`. Used to measure the achievable read bandwidth and to calibrate
+ * hardware byte counters against a copy of known size. */
+hmat_status hmat_probe_bandwidth(const void *src, void *dst, int64_t bytes, int32_t mode,
+                                 void *stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *hmat_last_error(void);
+
+/* Name of a status code. */
+const char *hmat_status_string(hmat_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H_ */

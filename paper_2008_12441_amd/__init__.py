@@ -1,0 +1,19 @@
+"""MI355X (gfx950) H-matrix-vector product under weak admissibility.
+
+The product y = alpha K x + beta y of an H-matrix (Def. 2.3, Eq. (2.4)) runs
+in hand-written HIP kernels behind the C ABI of ``include/hmat.h``; this
+package is the thin Python binding of that library (``binding``) and its
+build step (``_build``).
+"""
+from .binding import (BLOCK_DTYPE, EXPORTED, HMAT_STORE_FP16_SCALED, HMAT_STORE_FP32, LIB_PATH, STORAGE,
+                      HMatrix, HmatError, hmat_create, hmat_destroy, hmat_get_info, hmat_get_timing,
+                      hmat_last_error, hmat_matvec, hmat_probe_bandwidth, hmat_set_timing,
+                      hmat_status_string, load_library, make_block_array, make_descriptors,
+                      make_tree_desc)
+
+__all__ = [
+    "BLOCK_DTYPE", "EXPORTED", "HMAT_STORE_FP16_SCALED", "HMAT_STORE_FP32", "LIB_PATH", "STORAGE", "HMatrix",
+    "HmatError", "hmat_create", "hmat_destroy", "hmat_get_info", "hmat_get_timing", "hmat_last_error",
+    "hmat_matvec", "hmat_probe_bandwidth", "hmat_set_timing", "hmat_status_string", "load_library",
+    "make_block_array", "make_descriptors", "make_tree_desc",
+]

@@ -1,0 +1,268 @@
+"""ctypes binding of libhmat (include/hmat.h): argument marshalling only.
+
+Every function keeps the C name and raises ``HmatError`` on a non-OK status.
+All arithmetic runs in the library's HIP kernels; if the built library is
+missing, loading fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libhmat.so")
+
+HMAT_OK = 0
+HMAT_ERR_INVALID_ARG = 1
+HMAT_ERR_BAD_TREE = 2
+HMAT_ERR_BAD_BLOCKS = 3
+HMAT_ERR_UNSUPPORTED = 4
+HMAT_ERR_NOMEM = 5
+HMAT_ERR_DEVICE = 6
+
+HMAT_STORE_FP32 = 0
+HMAT_STORE_FP16_SCALED = 1
+STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED}
+
+HMAT_NUM_PHASES = 3
+
+
+class hmat_tree_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("num_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("parent", ctypes.c_void_p), ("begin", ctypes.c_void_p), ("end", ctypes.c_void_p)]
+
+
+class hmat_block_desc(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_int32), ("source", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("a", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("ldb", ctypes.c_int64)]
+
+
+class hmat_options(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class hmat_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("leaf_depth", ctypes.c_int32), ("num_chunks", ctypes.c_int32),
+                ("num_dense_blocks", ctypes.c_int64), ("num_lowrank_blocks", ctypes.c_int64),
+                ("stored_elements", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("device_factor_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("storage", ctypes.c_int32), ("max_nrhs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# numpy twin of hmat_block_desc, so large block lists are built without Python loops
+BLOCK_DTYPE = np.dtype([("target", np.int32), ("source", np.int32), ("rank", np.int32),
+                        ("reserved", np.int32), ("a", np.uint64), ("lda", np.int64),
+                        ("b", np.uint64), ("ldb", np.int64)], align=True)
+assert BLOCK_DTYPE.itemsize == ctypes.sizeof(hmat_block_desc)
+
+EXPORTED = ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
+            "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string")
+
+
+class HmatError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{_status_name(status)}: {message}")
+
+
+_lib = None
+
+
+def _status_name(status):
+    names = {0: "HMAT_OK", 1: "HMAT_ERR_INVALID_ARG", 2: "HMAT_ERR_BAD_TREE", 3: "HMAT_ERR_BAD_BLOCKS",
+             4: "HMAT_ERR_UNSUPPORTED", 5: "HMAT_ERR_NOMEM", 6: "HMAT_ERR_DEVICE"}
+    return names.get(status, f"status {status}")
+
+
+def load_library(path: str | None = None):
+    """Load libhmat.so (built by ``__graft_entry__.build()``); raises if it is missing."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libhmat is not built ({p} missing): run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.hmat_create.argtypes = [ctypes.POINTER(hmat_tree_desc), vp, i64, ctypes.POINTER(hmat_options),
+                                ctypes.POINTER(vp)]
+    lib.hmat_matvec.argtypes = [vp, i32, ctypes.c_float, vp, i64, ctypes.c_float, vp, i64, vp]
+    lib.hmat_destroy.argtypes = [vp]
+    lib.hmat_get_info.argtypes = [vp, ctypes.POINTER(hmat_info)]
+    lib.hmat_set_timing.argtypes = [vp, i32]
+    lib.hmat_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.hmat_probe_bandwidth.argtypes = [vp, vp, i64, i32, vp]
+    lib.hmat_last_error.restype = ctypes.c_char_p
+    lib.hmat_status_string.restype = ctypes.c_char_p
+    lib.hmat_status_string.argtypes = [ctypes.c_int]
+    for name in ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
+                 "hmat_get_timing", "hmat_probe_bandwidth"):
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != HMAT_OK:
+        raise HmatError(status, hmat_last_error())
+
+
+def hmat_last_error() -> str:
+    return load_library().hmat_last_error().decode()
+
+
+def hmat_status_string(status: int) -> str:
+    return load_library().hmat_status_string(status).decode()
+
+
+def make_tree_desc(parent, begin, end):
+    """hmat_tree_desc over numpy arrays (kept alive on the returned object)."""
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    begin = np.ascontiguousarray(begin, dtype=np.int64)
+    end = np.ascontiguousarray(end, dtype=np.int64)
+    d = hmat_tree_desc(int(end[0] - begin[0]), len(parent), 0, parent.ctypes.data, begin.ctypes.data,
+                       end.ctypes.data)
+    d._keep = (parent, begin, end)
+    return d
+
+
+def make_block_array(target, source, rank, pool, off_a, off_b, size_t, size_s):
+    """hmat_block_desc records for factors packed in one FP32 pool.
+
+    Block b: dense D (|t| x |s|, ld |t|) or U (|t| x r, ld |t|) at pool[off_a[b]];
+    V (|s| x r, ld |s|) at pool[off_b[b]]. ``size_t``/``size_s`` are |t| and |s|.
+    """
+    pool = np.ascontiguousarray(pool, dtype=np.float32)
+    nb = len(target)
+    arr = np.zeros(nb, dtype=BLOCK_DTYPE)
+    base = pool.ctypes.data
+    rank = np.asarray(rank, dtype=np.int32)
+    arr["target"] = target
+    arr["source"] = source
+    arr["rank"] = rank
+    arr["a"] = base + np.asarray(off_a, np.int64).astype(np.uint64) * np.uint64(4)
+    arr["lda"] = size_t
+    lowrank = rank > 0
+    arr["b"] = np.where(lowrank, base + np.maximum(np.asarray(off_b, np.int64), 0).astype(np.uint64) * np.uint64(4),
+                        np.uint64(0))
+    arr["ldb"] = np.where(lowrank, size_s, 0)
+    return arr, pool
+
+
+def hmat_create(tree_desc: hmat_tree_desc, blocks: np.ndarray, *, storage: int = HMAT_STORE_FP32,
+                max_nrhs: int = 1, device: int = 0, flags: int = 0) -> int:
+    """Create a handle; ``blocks`` is a BLOCK_DTYPE array. Returns the handle (an int)."""
+    lib = load_library()
+    blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
+    opts = hmat_options(int(storage), int(max_nrhs), int(device), int(flags))
+    out = ctypes.c_void_p()
+    _check(lib.hmat_create(ctypes.byref(tree_desc), blocks.ctypes.data if len(blocks) else None,
+                           len(blocks), ctypes.byref(opts), ctypes.byref(out)))
+    return out.value
+
+
+def hmat_matvec(h: int, nrhs: int, alpha: float, x_ptr: int, ldx: int, beta: float, y_ptr: int, ldy: int,
+                stream: int | None = None):
+    _check(load_library().hmat_matvec(h, int(nrhs), float(alpha), x_ptr, int(ldx), float(beta), y_ptr,
+                                      int(ldy), stream))
+
+
+def hmat_destroy(h: int | None):
+    _check(load_library().hmat_destroy(h))
+
+
+def hmat_get_info(h: int) -> dict:
+    info = hmat_info()
+    _check(load_library().hmat_get_info(h, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def hmat_set_timing(h: int, enable: bool):
+    _check(load_library().hmat_set_timing(h, int(bool(enable))))
+
+
+def hmat_get_timing(h: int):
+    ms = (ctypes.c_double * HMAT_NUM_PHASES)()
+    calls = ctypes.c_int64()
+    _check(load_library().hmat_get_timing(h, ms, ctypes.byref(calls)))
+    return list(ms), calls.value
+
+
+def hmat_probe_bandwidth(src_ptr: int, dst_ptr: int, nbytes: int, mode: int, stream: int | None = None):
+    _check(load_library().hmat_probe_bandwidth(src_ptr, dst_ptr, int(nbytes), int(mode), stream))
+
+
+class HMatrix:
+    """Owner of one handle; matvec takes torch CUDA tensors (n x k, column-major or a vector)."""
+
+    def __init__(self, tree_desc, blocks, *, storage="fp32", max_nrhs=1, device=0):
+        st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.handle = hmat_create(tree_desc, blocks, storage=st, max_nrhs=max_nrhs, device=device)
+        self.info = hmat_get_info(self.handle)
+        self.n = int(self.info["n"])
+
+    def matvec(self, x, y, *, alpha=1.0, beta=0.0, stream=None):
+        import torch
+
+        if not (x.is_cuda and y.is_cuda) or x.dtype != torch.float32 or y.dtype != torch.float32:
+            raise ValueError("x and y must be float32 CUDA tensors")
+        k = 1 if x.dim() == 1 else x.shape[1]
+        ldx = self._ld(x)
+        ldy = self._ld(y)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        hmat_matvec(self.handle, k, alpha, x.data_ptr(), ldx, beta, y.data_ptr(), ldy, stream)
+        return y
+
+    def _ld(self, t):
+        if t.shape[0] != self.n:
+            raise ValueError("vector length does not match n")
+        if t.dim() == 1:
+            if t.stride(0) != 1:
+                raise ValueError("vectors must be contiguous")
+            return self.n
+        if t.stride(0) != 1:
+            raise ValueError("multi-RHS arrays must be column-major (stride(0) == 1)")
+        return t.stride(1) if t.shape[1] > 1 else max(self.n, t.stride(1))
+
+    def close(self):
+        if self.handle:
+            hmat_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_descriptors(parent, begin, end, target, source, rank, pool, off_a, off_b):
+    """Tree descriptor and block records for a domain tree plus a packed FP32 factor pool.
+
+    ``parent/begin/end`` describe the tree (node 0 = root), ``target/source/rank``
+    the blocks, and ``off_a/off_b`` the element offsets of D or U and of V in
+    ``pool`` (see ``make_block_array``). Returns (tree_desc, block_array, keepalive).
+    """
+    begin = np.asarray(begin, np.int64)
+    end = np.asarray(end, np.int64)
+    size = end - begin
+    target = np.asarray(target, np.int32)
+    source = np.asarray(source, np.int32)
+    tree = make_tree_desc(parent, begin, end)
+    blocks, pool = make_block_array(target, source, rank, pool, off_a, off_b, size[target], size[source])
+    return tree, blocks, (tree, pool)

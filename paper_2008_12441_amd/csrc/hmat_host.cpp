@@ -1,0 +1,908 @@
+// Host side of libhmat: argument and structure validation, the level-ordered
+// device layout, host-side quantisation, device memory, kernel launches and
+// timing. The C ABI is declared in include/hmat.h.
+#include "hmat.h"
+#include "hmat_internal.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_set>
+#include <vector>
+
+using hmat::ChunkMeta;
+using hmat::DevPlan;
+using hmat::DSeg;
+using hmat::VTile;
+using hmat::ZItem;
+using hmat::ZItem2;
+using hmat::ZSeg;
+
+struct hmat_handle {
+    int32_t device = 0;
+    int32_t storage = 0;
+    int32_t max_nrhs = 1;
+    hmat_info info{};
+    DevPlan plan{};
+    std::vector<void *> dev_allocs;
+    // phase timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;   // HMAT_NUM_PHASES + 1 per timed column
+    size_t events_used = 0;
+    double ms[HMAT_NUM_PHASES] = {0, 0, 0};
+    int64_t timed_calls = 0;
+};
+
+namespace {
+
+thread_local std::string t_err;
+std::mutex g_mu;
+std::unordered_set<const hmat_handle *> g_live;
+
+hmat_status fail(hmat_status s, const std::string &msg) {
+    t_err = msg;
+    return s;
+}
+
+bool is_live(const hmat_handle *h) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_live.count(h) != 0;
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 16u));
+    if (n < 2 || nt == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    nt = (unsigned)std::min<int64_t>(nt, n);
+    std::atomic<int64_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            int64_t i = next.fetch_add(1);
+            if (i >= n) break;
+            f(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned k = 1; k < nt; ++k) th.emplace_back(worker);
+    worker();
+    for (auto &t : th) t.join();
+}
+
+// ---------------------------------------------------------------------------
+// FP16 quantisation (host, bit-defined): power-of-two scale per stored array,
+// s = 2^(ceil(log2 amax) - 15), q = round-to-nearest-even(v / s) in IEEE half.
+// |v / s| <= 2^15 < 65504, and q * s reproduces the stored value exactly.
+// ---------------------------------------------------------------------------
+uint16_t f32_to_f16_rne(float v) {
+    uint32_t x;
+    std::memcpy(&x, &v, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    const uint32_t ax = x & 0x7fffffffu;
+    if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
+    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to infinity
+    if (ax < 0x38800000u) {                                    // half subnormal range
+        const float f = std::fabs(v) * 16777216.0f;            // exact: units of 2^-24
+        return (uint16_t)(sign | (uint32_t)std::nearbyint(f));
+    }
+    const uint32_t mant = ax & 0x7fffffu;
+    const uint32_t exp = (ax >> 23) - 127 + 15;
+    uint32_t h = (exp << 10) | (mant >> 13);
+    const uint32_t rem = mant & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h += 1;
+    return (uint16_t)(sign | h);
+}
+
+float pow2_scale_f16(float amax) {
+    if (!(amax > 0.0f)) return 1.0f;
+    int e = 0;
+    const float m = std::frexp(amax, &e);  // amax = m 2^e, m in [0.5, 1)
+    const int c = (m == 0.5f) ? e - 1 : e; // ceil(log2 amax)
+    return std::ldexp(1.0f, std::max(c - 15, -126));
+}
+
+float col_major_amax(const float *a, int64_t rows, int64_t cols, int64_t ld, bool *finite) {
+    float m = 0.0f;
+    for (int64_t j = 0; j < cols; ++j)
+        for (int64_t i = 0; i < rows; ++i) {
+            const float v = a[i + j * ld];
+            if (!std::isfinite(v)) *finite = false;
+            m = std::max(m, std::fabs(v));
+        }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Tree analysis and structure validation.
+// ---------------------------------------------------------------------------
+struct Tree {
+    int64_t n = 0;
+    int32_t num_nodes = 0;
+    std::vector<int32_t> parent, depth, child_start, child_list, child_pos;
+    std::vector<int64_t> begin, end;
+    int32_t L = 0;
+    int32_t nkids(int32_t p) const { return child_start[p + 1] - child_start[p]; }
+    int32_t kid(int32_t p, int32_t i) const { return child_list[child_start[p] + i]; }
+    bool leaf(int32_t p) const { return nkids(p) == 0; }
+    int64_t size(int32_t p) const { return end[p] - begin[p]; }
+};
+
+hmat_status analyse_tree(const hmat_tree_desc *td, Tree &t) {
+    if (!td) return fail(HMAT_ERR_INVALID_ARG, "tree descriptor is NULL");
+    if (td->n < 1 || td->n >= (int64_t(1) << 31))
+        return fail(HMAT_ERR_INVALID_ARG, "tree n must be in [1, 2^31)");
+    if (td->num_nodes < 1) return fail(HMAT_ERR_INVALID_ARG, "tree needs at least one node");
+    if (td->reserved != 0) return fail(HMAT_ERR_INVALID_ARG, "tree reserved field must be 0");
+    if (!td->parent || !td->begin || !td->end)
+        return fail(HMAT_ERR_INVALID_ARG, "tree arrays must not be NULL");
+    const int32_t nn = td->num_nodes;
+    t.n = td->n;
+    t.num_nodes = nn;
+    t.parent.assign(td->parent, td->parent + nn);
+    t.begin.assign(td->begin, td->begin + nn);
+    t.end.assign(td->end, td->end + nn);
+    if (t.parent[0] != -1) return fail(HMAT_ERR_BAD_TREE, "node 0 must be the root (parent -1)");
+    if (t.begin[0] != 0 || t.end[0] != t.n)
+        return fail(HMAT_ERR_BAD_TREE, "the root must own [0, n)");
+    std::vector<int32_t> count(nn + 1, 0);
+    for (int32_t i = 0; i < nn; ++i) {
+        if (t.begin[i] < 0 || t.end[i] > t.n || t.begin[i] >= t.end[i])
+            return fail(HMAT_ERR_BAD_TREE, "node " + std::to_string(i) + " has an empty or out-of-range index range");
+        if (i > 0) {
+            if (t.parent[i] < 0 || t.parent[i] >= i)
+                return fail(HMAT_ERR_BAD_TREE, "node " + std::to_string(i) + " must have a parent with a smaller id");
+            count[t.parent[i]]++;
+        }
+    }
+    t.child_start.assign(nn + 1, 0);
+    for (int32_t i = 0; i < nn; ++i) t.child_start[i + 1] = t.child_start[i] + count[i];
+    t.child_list.assign(std::max(nn - 1, 0), 0);
+    t.child_pos.assign(nn, 0);
+    std::vector<int32_t> fill(nn, 0);
+    for (int32_t i = 1; i < nn; ++i) {
+        const int32_t p = t.parent[i];
+        t.child_pos[i] = fill[p];
+        t.child_list[t.child_start[p] + fill[p]++] = i;
+    }
+    t.depth.assign(nn, 0);
+    for (int32_t i = 1; i < nn; ++i) t.depth[i] = t.depth[t.parent[i]] + 1;
+    // children (in id order) tile the parent's range contiguously
+    for (int32_t p = 0; p < nn; ++p) {
+        const int32_t k = t.nkids(p);
+        if (k == 0) continue;
+        int64_t cur = t.begin[p];
+        for (int32_t c = 0; c < k; ++c) {
+            const int32_t ch = t.kid(p, c);
+            if (t.begin[ch] != cur)
+                return fail(HMAT_ERR_BAD_TREE, "children of node " + std::to_string(p) + " do not tile its range in id order");
+            cur = t.end[ch];
+        }
+        if (cur != t.end[p])
+            return fail(HMAT_ERR_BAD_TREE, "children of node " + std::to_string(p) + " do not cover its range");
+    }
+    int32_t L = -1;
+    for (int32_t i = 0; i < nn; ++i) {
+        if (!t.leaf(i)) continue;
+        if (L < 0) L = t.depth[i];
+        else if (t.depth[i] != L)
+            return fail(HMAT_ERR_UNSUPPORTED, "leaves at different depths are not supported (the weak-admissibility "
+                                              "structure then has dense blocks between a leaf and a non-leaf)");
+    }
+    t.L = L;
+    return HMAT_OK;
+}
+
+struct Structure {
+    std::vector<int64_t> slot_base;  // per node: offset into slot (k^2 pairs of its children)
+    std::vector<int64_t> slot;       // block index per ordered child pair, -1 if absent
+    int64_t block_of(const Tree &t, int32_t a, int32_t b) const {
+        const int32_t p = t.parent[a];
+        return slot[slot_base[p] + (int64_t)t.child_pos[a] * t.nkids(p) + t.child_pos[b]];
+    }
+};
+
+hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb, Structure &st) {
+    if (!bl) return fail(HMAT_ERR_INVALID_ARG, "blocks pointer is NULL");
+    if (nb < 1) return fail(HMAT_ERR_INVALID_ARG, "num_blocks must be >= 1");
+    const int32_t nn = t.num_nodes;
+    for (int64_t b = 0; b < nb; ++b) {
+        const hmat_block_desc &d = bl[b];
+        const std::string id = "block " + std::to_string(b);
+        if (d.reserved != 0) return fail(HMAT_ERR_INVALID_ARG, id + ": reserved field must be 0");
+        if (d.target < 0 || d.target >= nn || d.source < 0 || d.source >= nn)
+            return fail(HMAT_ERR_INVALID_ARG, id + ": node id out of range");
+        if (d.rank < 0) return fail(HMAT_ERR_INVALID_ARG, id + ": negative rank");
+        if (!d.a) return fail(HMAT_ERR_INVALID_ARG, id + ": factor pointer a is NULL");
+        const int64_t mt = t.size(d.target), ms = t.size(d.source);
+        if (d.lda < mt) return fail(HMAT_ERR_INVALID_ARG, id + ": lda < |t|");
+        if (d.rank > 0) {
+            if (!d.b) return fail(HMAT_ERR_INVALID_ARG, id + ": factor pointer b is NULL");
+            if (d.ldb < ms) return fail(HMAT_ERR_INVALID_ARG, id + ": ldb < |s|");
+            if (d.rank > std::min(mt, ms)) return fail(HMAT_ERR_INVALID_ARG, id + ": rank exceeds min(|t|, |s|)");
+        }
+    }
+    if (t.L == 0) {
+        if (nb != 1 || bl[0].target != 0 || bl[0].source != 0 || bl[0].rank != 0)
+            return fail(HMAT_ERR_BAD_BLOCKS, "a tree whose root is a leaf takes exactly one dense block (0, 0)");
+        return HMAT_OK;
+    }
+    st.slot_base.assign(nn + 1, 0);
+    for (int32_t p = 0; p < nn; ++p)
+        st.slot_base[p + 1] = st.slot_base[p] + (int64_t)t.nkids(p) * t.nkids(p);
+    st.slot.assign(st.slot_base[nn], -1);
+    for (int64_t b = 0; b < nb; ++b) {
+        const hmat_block_desc &d = bl[b];
+        const std::string id = "block " + std::to_string(b) + " (" + std::to_string(d.target) + ", " +
+                               std::to_string(d.source) + ")";
+        if (d.target == 0 || d.source == 0)
+            return fail(HMAT_ERR_BAD_BLOCKS, id + ": the root pair is never a block of Def. 2.3");
+        const int32_t p = t.parent[d.target];
+        if (t.parent[d.source] != p)
+            return fail(HMAT_ERR_UNSUPPORTED, id + ": blocks between non-siblings (standard admissibility) are not supported");
+        if (t.depth[p] == t.L - 1) {
+            if (d.rank != 0)
+                return fail(HMAT_ERR_UNSUPPORTED, id + ": low-rank blocks between leaves are not supported (Def. 2.3 makes them dense)");
+        } else {
+            if (d.target == d.source)
+                return fail(HMAT_ERR_BAD_BLOCKS, id + ": (c, c) above the leaves is a recursion pair, not a block");
+            if (d.rank == 0)
+                return fail(HMAT_ERR_UNSUPPORTED, id + ": dense blocks between non-leaf siblings are not supported");
+        }
+        int64_t &s = st.slot[st.slot_base[p] + (int64_t)t.child_pos[d.target] * t.nkids(p) + t.child_pos[d.source]];
+        if (s >= 0) return fail(HMAT_ERR_BAD_BLOCKS, id + ": duplicate block");
+        s = b;
+    }
+    for (int32_t p = 0; p < nn; ++p) {
+        const int32_t k = t.nkids(p);
+        if (k == 0) continue;
+        const bool leaf_parent = t.depth[p] == t.L - 1;
+        for (int32_t i = 0; i < k; ++i)
+            for (int32_t j = 0; j < k; ++j) {
+                if (!leaf_parent && i == j) continue;
+                if (st.slot[st.slot_base[p] + (int64_t)i * k + j] < 0)
+                    return fail(HMAT_ERR_BAD_BLOCKS, "missing block (" + std::to_string(t.kid(p, i)) + ", " +
+                                                         std::to_string(t.kid(p, j)) + ")");
+            }
+    }
+    return HMAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Level-ordered layout.
+// ---------------------------------------------------------------------------
+struct HostPlan {
+    int32_t vw = 4;                 // elements per 16-byte vector
+    int32_t chunk_depth = 0;
+    std::vector<int32_t> chunk_node;
+    std::vector<ChunkMeta> chunks;
+    std::vector<ZSeg> zsegs;
+    std::vector<DSeg> dsegs;
+    std::vector<float> dscale;
+    std::vector<VTile> vtiles;
+    std::vector<ZItem> z1;
+    std::vector<ZItem2> z2;
+    std::vector<int32_t> anc;       // chunk x chunk_depth+1: ancestor at each depth
+    std::vector<int32_t> vcol;      // per block
+    std::vector<int32_t> zdst;      // per block
+    std::vector<int32_t> zoff, zlen; // per node
+    std::vector<float> sU, sV, sD;  // per block scales
+    int64_t v_elems = 0, ud_elems = 0;
+    int64_t part_floats = 0, slice_floats = 0, zg_floats = 0;
+    int32_t lds_floats = 0, max_leaf_rows = 0;
+};
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
+                       int32_t storage, HostPlan &hp) {
+    hp.vw = storage == HMAT_STORE_FP16_SCALED ? 8 : 4;
+    const int32_t vw = hp.vw;
+    const int32_t L = t.L;
+    const int32_t cd = std::max(L - 1, 0);
+    hp.chunk_depth = cd;
+    for (int32_t i = 0; i < t.num_nodes; ++i)
+        if (t.depth[i] == cd) hp.chunk_node.push_back(i);
+    std::sort(hp.chunk_node.begin(), hp.chunk_node.end(),
+              [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
+    const int32_t nc = (int32_t)hp.chunk_node.size();
+    hp.anc.assign((size_t)nc * (cd + 1), 0);
+    // chunk range of every node at depth <= cd
+    std::vector<int32_t> cfirst(t.num_nodes, INT32_MAX), clast(t.num_nodes, -1);
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t a = hp.chunk_node[c];
+        for (int32_t d = cd; d >= 0; --d) {
+            hp.anc[(size_t)c * (cd + 1) + d] = a;
+            cfirst[a] = std::min(cfirst[a], c);
+            clast[a] = std::max(clast[a], c + 1);
+            a = t.parent[a];
+        }
+    }
+    auto rank_of = [&](int64_t b) { return bl[b].rank; };
+
+    // per-block scales
+    hp.sU.assign(nb, 1.0f);
+    hp.sV.assign(nb, 1.0f);
+    hp.sD.assign(nb, 1.0f);
+    if (storage == HMAT_STORE_FP16_SCALED) {
+        std::atomic<bool> ok{true};
+        parallel_for(nb, [&](int64_t b) {
+            bool fin = true;
+            const hmat_block_desc &d = bl[b];
+            const int64_t mt = t.size(d.target), ms = t.size(d.source);
+            if (d.rank == 0) {
+                hp.sD[b] = pow2_scale_f16(col_major_amax(d.a, mt, ms, d.lda, &fin));
+            } else {
+                hp.sU[b] = pow2_scale_f16(col_major_amax(d.a, mt, d.rank, d.lda, &fin));
+                hp.sV[b] = pow2_scale_f16(col_major_amax(d.b, ms, d.rank, d.ldb, &fin));
+            }
+            if (!fin) ok = false;
+        });
+        if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
+    }
+
+    // z layout: per non-leaf node t at depth 1..L-1, the z vectors of its sibling blocks
+    hp.zoff.assign(t.num_nodes, 0);
+    hp.zlen.assign(t.num_nodes, 0);
+    hp.zdst.assign(nb, -1);
+    hp.vcol.assign(nb, -1);
+    int64_t zcur = 0;
+    for (int32_t a = 1; a < t.num_nodes && L >= 2; ++a) {
+        if (t.depth[a] < 1 || t.depth[a] > L - 1) continue;
+        const int32_t p = t.parent[a];
+        hp.zoff[a] = (int32_t)zcur;
+        int32_t off = 0;
+        for (int32_t j = 0; j < t.nkids(p); ++j) {
+            const int32_t s = t.kid(p, j);
+            if (s == a) continue;
+            const int64_t b = st.block_of(t, a, s);
+            hp.zdst[b] = (int32_t)(zcur + off);
+            off += rank_of(b);
+        }
+        hp.zlen[a] = off;
+        zcur += off;
+    }
+    hp.zg_floats = zcur;
+
+    // chunks
+    hp.chunks.resize(nc);
+    int64_t ud_cur = 0, part_cur = 0;
+    int32_t max_lds = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t node = hp.chunk_node[c];
+        ChunkMeta &m = hp.chunks[c];
+        std::memset(&m, 0, sizeof(m));
+        m.row_begin = (int32_t)t.begin[node];
+        m.rows = (int32_t)t.size(node);
+        // V columns (source side) and their offsets
+        int32_t wv = 0;
+        for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+            const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
+            const int32_t p = t.parent[a];
+            for (int32_t j = 0; j < t.nkids(p); ++j) {
+                const int32_t tt = t.kid(p, j);
+                if (tt == a) continue;
+                const int64_t b = st.block_of(t, tt, a);
+                if (hp.vcol[b] < 0) hp.vcol[b] = wv;
+                else if (hp.vcol[b] != wv)
+                    return fail(HMAT_ERR_UNSUPPORTED, "inconsistent source column layout");
+                wv += rank_of(b);
+            }
+        }
+        const int32_t ncb = (wv + hmat::kWave - 1) / hmat::kWave;
+        const int32_t nvec = (m.rows + vw - 1) / vw;
+        m.part_base = (int32_t)part_cur;
+        for (int32_t cb = 0; cb < ncb; ++cb) {
+            VTile vt;
+            vt.off = hp.v_elems;
+            vt.chunk = c;
+            vt.pout = (int32_t)(part_cur + (int64_t)cb * hmat::kWave);
+            hp.vtiles.push_back(vt);
+            hp.v_elems += (int64_t)nvec * hmat::kWave * vw;
+        }
+        part_cur += (int64_t)ncb * hmat::kWave;
+        // U columns (target side): z segments of each ancestor level
+        m.zseg_base = (int32_t)hp.zsegs.size();
+        int32_t wlr = 0;
+        for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+            const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
+            hp.zsegs.push_back(ZSeg{hp.zoff[a], hp.zlen[a]});
+            wlr += hp.zlen[a];
+        }
+        m.nq_lr = (wlr + vw - 1) / vw;
+        // dense part: one segment per leaf (the chunk's children, or the root itself)
+        m.dseg_base = (int32_t)hp.dsegs.size();
+        std::vector<int32_t> leaves;
+        if (L == 0) leaves.push_back(node);
+        else
+            for (int32_t j = 0; j < t.nkids(node); ++j) leaves.push_back(t.kid(node, j));
+        m.nleaf = (int32_t)leaves.size();
+        int32_t nq = m.nq_lr;
+        for (int32_t lf : leaves) {
+            DSeg ds;
+            ds.row_begin = (int32_t)t.begin[lf];
+            ds.rows = (int32_t)t.size(lf);
+            ds.nq = (ds.rows + vw - 1) / vw;
+            ds.pad_ = 0;
+            nq += ds.nq;
+            hp.dsegs.push_back(ds);
+            hp.max_leaf_rows = std::max(hp.max_leaf_rows, ds.rows);
+        }
+        m.nq = nq;
+        m.dscale_base = (int32_t)hp.dscale.size();
+        for (int32_t it = 0; it < m.nleaf; ++it)
+            for (int32_t is = 0; is < m.nleaf; ++is) {
+                int64_t b = (L == 0) ? 0 : st.block_of(t, leaves[it], leaves[is]);
+                hp.dscale.push_back(hp.sD[b]);
+            }
+        m.ud_off = ud_cur;
+        const int32_t ntile = (m.rows + hmat::kWave - 1) / hmat::kWave;
+        ud_cur += (int64_t)ntile * nq * hmat::kWave * vw;
+        max_lds = std::max(max_lds, nq * vw);
+    }
+    hp.ud_elems = ud_cur;
+    hp.part_floats = part_cur;
+    hp.lds_floats = max_lds;
+    if (max_lds > hmat::kMaxLdsFloats)
+        return fail(HMAT_ERR_UNSUPPORTED, "a chunk's vector operand (" + std::to_string(max_lds) +
+                                              " floats) exceeds the U-phase LDS budget");
+    if (hp.part_floats >= INT32_MAX || hp.zg_floats >= INT32_MAX)
+        return fail(HMAT_ERR_UNSUPPORTED, "workspace too large");
+
+    // partial reduction items: slices of at most 32 chunks; slice sums live in
+    // the same buffer as z, after it
+    const int32_t S = 32;
+    int64_t slice_cur = hp.zg_floats;
+    for (int64_t b = 0; b < nb && L >= 2; ++b) {
+        if (bl[b].rank == 0) continue;
+        const int32_t s = bl[b].source;
+        const int32_t c0 = cfirst[s], c1 = clast[s];
+        const int32_t r = bl[b].rank;
+        const float scale = hp.sU[b] * hp.sV[b];
+        if (c1 - c0 <= S) {
+            hp.z1.push_back(ZItem{c0, c1 - c0, hp.vcol[b], r, hp.zdst[b], scale});
+        } else {
+            const int32_t nsl = (c1 - c0 + S - 1) / S;
+            for (int32_t k = 0; k < nsl; ++k) {
+                const int32_t a0 = c0 + k * S;
+                hp.z1.push_back(ZItem{a0, std::min(S, c1 - a0), hp.vcol[b], r,
+                                      (int32_t)(slice_cur + (int64_t)k * r), 1.0f});
+            }
+            hp.z2.push_back(ZItem2{(int32_t)slice_cur, nsl, r, hp.zdst[b], scale, 0});
+            slice_cur += (int64_t)nsl * r;
+        }
+    }
+    hp.slice_floats = slice_cur - hp.zg_floats;
+    if (slice_cur >= INT32_MAX) return fail(HMAT_ERR_UNSUPPORTED, "workspace too large");
+    return HMAT_OK;
+}
+
+// Fill the V panel (FP32 or FP16) for the chunks [c_lo, c_hi).
+template <class T>
+void fill_v(const Tree &t, const Structure &st, const hmat_block_desc *bl, const HostPlan &hp,
+            T *out, int64_t base_elem) {
+    const int32_t vw = hp.vw;
+    const int32_t cd = hp.chunk_depth;
+    const int32_t L = t.L;
+    // first vtile of each chunk
+    std::vector<int32_t> first(hp.chunks.size() + 1, (int32_t)hp.vtiles.size());
+    for (int32_t i = (int32_t)hp.vtiles.size() - 1; i >= 0; --i) first[hp.vtiles[i].chunk] = i;
+    for (int32_t c = (int32_t)hp.chunks.size() - 1; c >= 0; --c)
+        first[c] = std::min(first[c], first[c + 1]);
+    parallel_for((int64_t)hp.chunks.size(), [&](int64_t c) {
+        const ChunkMeta &m = hp.chunks[c];
+        if (first[c] >= (int32_t)hp.vtiles.size() || hp.vtiles[first[c]].chunk != c) return;
+        const int32_t nvec = (m.rows + vw - 1) / vw;
+        int32_t col = 0;
+        for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+            const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
+            const int32_t p = t.parent[a];
+            const int64_t roff = m.row_begin - t.begin[a];
+            for (int32_t j = 0; j < t.nkids(p); ++j) {
+                const int32_t tt = t.kid(p, j);
+                if (tt == a) continue;
+                const int64_t b = st.block_of(t, tt, a);
+                const hmat_block_desc &d = bl[b];
+                const float inv = 1.0f / hp.sV[b];
+                for (int32_t k = 0; k < d.rank; ++k, ++col) {
+                    const VTile &vt = hp.vtiles[first[c] + col / hmat::kWave];
+                    T *dst = out + (vt.off - base_elem);
+                    const int32_t l = col % hmat::kWave;
+                    const float *src = d.b + roff + (int64_t)k * d.ldb;
+                    for (int32_t i = 0; i < nvec * vw; ++i) {
+                        const float v = i < m.rows ? src[i] : 0.0f;
+                        T q;
+                        if constexpr (sizeof(T) == 4) q = v;
+                        else q = f32_to_f16_rne(v * inv);
+                        dst[((int64_t)(i / vw) * hmat::kWave + l) * vw + i % vw] = q;
+                    }
+                }
+            }
+        }
+    });
+}
+
+template <class T>
+void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, const HostPlan &hp,
+             T *out) {
+    const int32_t vw = hp.vw;
+    const int32_t cd = hp.chunk_depth;
+    const int32_t L = t.L;
+    parallel_for((int64_t)hp.chunks.size(), [&](int64_t c) {
+        const ChunkMeta &m = hp.chunks[c];
+        const int64_t tile_stride = (int64_t)m.nq * hmat::kWave * vw;
+        auto put = [&](int32_t i, int32_t j, T q) {
+            out[m.ud_off + (i / hmat::kWave) * tile_stride +
+                ((int64_t)(j / vw) * hmat::kWave + i % hmat::kWave) * vw + j % vw] = q;
+        };
+        const int32_t ntile = (m.rows + hmat::kWave - 1) / hmat::kWave;
+        const int32_t prow = ntile * hmat::kWave;
+        int32_t col = 0;
+        for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+            const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
+            const int32_t p = t.parent[a];
+            const int64_t roff = m.row_begin - t.begin[a];
+            for (int32_t j = 0; j < t.nkids(p); ++j) {
+                const int32_t s = t.kid(p, j);
+                if (s == a) continue;
+                const int64_t b = st.block_of(t, a, s);
+                const hmat_block_desc &d = bl[b];
+                const float inv = 1.0f / hp.sU[b];
+                for (int32_t k = 0; k < d.rank; ++k, ++col) {
+                    const float *src = d.a + roff + (int64_t)k * d.lda;
+                    for (int32_t i = 0; i < prow; ++i) {
+                        const float v = i < m.rows ? src[i] : 0.0f;
+                        if constexpr (sizeof(T) == 4) put(i, col, v);
+                        else put(i, col, f32_to_f16_rne(v * inv));
+                    }
+                }
+            }
+        }
+        for (; col < m.nq_lr * vw; ++col)
+            for (int32_t i = 0; i < prow; ++i) put(i, col, T(0));
+        // dense part, grouped by source leaf
+        int32_t qcol = m.nq_lr * vw;
+        for (int32_t is = 0; is < m.nleaf; ++is) {
+            const DSeg &sseg = hp.dsegs[m.dseg_base + is];
+            for (int32_t jj = 0; jj < sseg.nq * vw; ++jj, ++qcol) {
+                for (int32_t it = 0, i = 0; i < prow; ++i) {
+                    float v = 0.0f;
+                    float inv = 1.0f;
+                    if (i < m.rows && jj < sseg.rows) {
+                        while (it + 1 < m.nleaf &&
+                               m.row_begin + i >= hp.dsegs[m.dseg_base + it + 1].row_begin)
+                            ++it;
+                        const DSeg &tseg = hp.dsegs[m.dseg_base + it];
+                        int64_t b = 0;
+                        if (L > 0) {
+                            const int32_t node = hp.chunk_node[c];
+                            b = st.block_of(t, t.kid(node, it), t.kid(node, is));
+                        }
+                        const hmat_block_desc &d = bl[b];
+                        v = d.a[(m.row_begin + i - tseg.row_begin) + (int64_t)jj * d.lda];
+                        inv = 1.0f / hp.sD[b];
+                    }
+                    if constexpr (sizeof(T) == 4) put(i, qcol, v);
+                    else put(i, qcol, f32_to_f16_rne(v * inv));
+                }
+            }
+        }
+    });
+}
+
+void release(hmat_handle *h) {
+    if (!h) return;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    for (void *p : h->dev_allocs) (void)hipFree(p);
+    delete h;
+}
+
+bool fault_alloc_armed() {
+    const char *e = std::getenv("HMAT_FAULT");
+    return e && std::strcmp(e, "alloc") == 0;
+}
+
+hmat_status dev_alloc(hmat_handle *h, size_t bytes, void **p) {
+    *p = nullptr;
+    if (fault_alloc_armed()) return fail(HMAT_ERR_NOMEM, "injected device allocation failure (HMAT_FAULT=alloc)");
+    if (h->dev_allocs.empty()) {
+        const hipError_t e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    const hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(HMAT_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes: out of memory");
+    }
+    if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    h->dev_allocs.push_back(*p);
+    return HMAT_OK;
+}
+
+template <class V>
+hmat_status upload(hmat_handle *h, const std::vector<V> &v, const V **dst) {
+    void *p = nullptr;
+    hmat_status s = dev_alloc(h, v.size() * sizeof(V), &p);
+    if (s != HMAT_OK) return s;
+    if (!v.empty()) {
+        const hipError_t e = hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    *dst = static_cast<const V *>(p);
+    return HMAT_OK;
+}
+
+template <class T>
+hmat_status upload_panels(hmat_handle *h, const Tree &t, const Structure &st,
+                          const hmat_block_desc *bl, const HostPlan &hp) {
+    void *vdev = nullptr, *uddev = nullptr;
+    hmat_status s = dev_alloc(h, hp.v_elems * sizeof(T), &vdev);
+    if (s != HMAT_OK) return s;
+    s = dev_alloc(h, hp.ud_elems * sizeof(T), &uddev);
+    if (s != HMAT_OK) return s;
+    try {
+        if (hp.v_elems > 0) {
+            std::vector<T> stage(hp.v_elems);
+            fill_v<T>(t, st, bl, hp, stage.data(), 0);
+            const hipError_t e = hipMemcpy(vdev, stage.data(), stage.size() * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        {
+            std::vector<T> stage(hp.ud_elems);
+            fill_ud<T>(t, st, bl, hp, stage.data());
+            const hipError_t e = hipMemcpy(uddev, stage.data(), stage.size() * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(HMAT_ERR_NOMEM, "host staging allocation failed");
+    }
+    h->plan.V = vdev;
+    h->plan.UD = uddev;
+    return HMAT_OK;
+}
+
+hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t nb,
+                        const hmat_options *opts, hmat_handle *h) {
+    if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
+    if (opts->storage != HMAT_STORE_FP32 && opts->storage != HMAT_STORE_FP16_SCALED)
+        return fail(HMAT_ERR_INVALID_ARG, "unknown storage form");
+    if (opts->max_nrhs < 1) return fail(HMAT_ERR_INVALID_ARG, "max_nrhs must be >= 1");
+    if (opts->device < 0) return fail(HMAT_ERR_INVALID_ARG, "device must be >= 0");
+    if (opts->flags != 0) return fail(HMAT_ERR_INVALID_ARG, "flags must be 0");
+    Tree t;
+    hmat_status s = analyse_tree(tree, t);
+    if (s != HMAT_OK) return s;
+    Structure st;
+    s = validate_blocks(t, blocks, nb, st);
+    if (s != HMAT_OK) return s;
+    HostPlan hp;
+    s = build_plan(t, st, blocks, nb, opts->storage, hp);
+    if (s != HMAT_OK) return s;
+
+    h->device = opts->device;
+    h->storage = opts->storage;
+    h->max_nrhs = opts->max_nrhs;
+    hmat_info &in = h->info;
+    in.n = t.n;
+    in.leaf_depth = t.L;
+    in.num_chunks = (int32_t)hp.chunks.size();
+    int64_t elems = 0, nd = 0, nl = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t mt = t.size(blocks[b].target), ms = t.size(blocks[b].source);
+        if (blocks[b].rank == 0) {
+            elems += mt * ms;
+            ++nd;
+        } else {
+            elems += (mt + ms) * blocks[b].rank;
+            ++nl;
+        }
+    }
+    in.num_dense_blocks = nd;
+    in.num_lowrank_blocks = nl;
+    in.stored_elements = elems;
+    const int64_t esz = opts->storage == HMAT_STORE_FP16_SCALED ? 2 : 4;
+    in.factor_bytes = elems * esz + (opts->storage == HMAT_STORE_FP16_SCALED ? 4 * (nd + 2 * nl) : 0);
+    in.device_factor_bytes = (hp.v_elems + hp.ud_elems) * esz;
+    in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * 4;
+    in.storage = opts->storage;
+    in.max_nrhs = opts->max_nrhs;
+
+    DevPlan &p = h->plan;
+    p.storage = opts->storage;
+    p.num_chunks = (int32_t)hp.chunks.size();
+    p.num_vtiles = (int32_t)hp.vtiles.size();
+    p.num_z1 = (int32_t)hp.z1.size();
+    p.num_z2 = (int32_t)hp.z2.size();
+    p.num_levels = std::max(t.L - 1, 0);
+    p.lds_floats = hp.lds_floats;
+    p.max_leaf_rows = hp.max_leaf_rows;
+
+    void *ws = nullptr;
+    if ((s = dev_alloc(h, hp.part_floats * 4, &ws)) != HMAT_OK) return s;
+    p.part = static_cast<float *>(ws);
+    if ((s = dev_alloc(h, (hp.zg_floats + hp.slice_floats) * 4, &ws)) != HMAT_OK) return s;
+    p.zg = static_cast<float *>(ws);
+    p.slice = p.zg + hp.zg_floats;
+    if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.zsegs, &p.zsegs)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.dsegs, &p.dsegs)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.dscale, &p.dscale)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.vtiles, &p.vtiles)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.z1, &p.z1)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.z2, &p.z2)) != HMAT_OK) return s;
+    if (opts->storage == HMAT_STORE_FP16_SCALED)
+        s = upload_panels<uint16_t>(h, t, st, blocks, hp);
+    else
+        s = upload_panels<float>(h, t, st, blocks, hp);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hmat_status_string(hmat_status s) {
+    switch (s) {
+    case HMAT_OK: return "HMAT_OK";
+    case HMAT_ERR_INVALID_ARG: return "HMAT_ERR_INVALID_ARG";
+    case HMAT_ERR_BAD_TREE: return "HMAT_ERR_BAD_TREE";
+    case HMAT_ERR_BAD_BLOCKS: return "HMAT_ERR_BAD_BLOCKS";
+    case HMAT_ERR_UNSUPPORTED: return "HMAT_ERR_UNSUPPORTED";
+    case HMAT_ERR_NOMEM: return "HMAT_ERR_NOMEM";
+    case HMAT_ERR_DEVICE: return "HMAT_ERR_DEVICE";
+    }
+    return "HMAT_ERR_UNKNOWN";
+}
+
+const char *hmat_last_error(void) { return t_err.c_str(); }
+
+hmat_status hmat_create(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t num_blocks,
+                        const hmat_options *opts, hmat_t *out) {
+    if (!out) return fail(HMAT_ERR_INVALID_ARG, "out pointer is NULL");
+    *out = nullptr;
+    t_err.clear();
+    hmat_handle *h = nullptr;
+    try {
+        h = new hmat_handle();
+        const hmat_status s = create_impl(tree, blocks, num_blocks, opts, h);
+        if (s != HMAT_OK) {
+            release(h);
+            return s;
+        }
+    } catch (const std::bad_alloc &) {
+        release(h);
+        return fail(HMAT_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        release(h);
+        return fail(HMAT_ERR_INVALID_ARG, std::string("internal error: ") + e.what());
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return HMAT_OK;
+}
+
+hmat_status hmat_destroy(hmat_t h) {
+    if (!h) return HMAT_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_live.erase(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown or already destroyed handle");
+    }
+    if (!h->dev_allocs.empty()) (void)hipSetDevice(h->device);
+    release(h);
+    return HMAT_OK;
+}
+
+hmat_status hmat_get_info(hmat_t h, hmat_info *info) {
+    if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
+    if (!info) return fail(HMAT_ERR_INVALID_ARG, "info pointer is NULL");
+    *info = h->info;
+    return HMAT_OK;
+}
+
+static hmat_status record_event(hmat_handle *h, hipStream_t stream) {
+    if (h->events_used == h->events.size()) {
+        hipEvent_t e;
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(err));
+        h->events.push_back(e);
+    }
+    const hipError_t err = hipEventRecord(h->events[h->events_used++], stream);
+    if (err != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(err));
+    return HMAT_OK;
+}
+
+hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
+                        float *y, int64_t ldy, void *stream) {
+    if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
+    const int64_t n = h->info.n;
+    if (nrhs < 1 || nrhs > h->max_nrhs) return fail(HMAT_ERR_INVALID_ARG, "nrhs out of [1, max_nrhs]");
+    if (!x || !y) return fail(HMAT_ERR_INVALID_ARG, "x and y must not be NULL");
+    if (ldx < n || ldy < n) return fail(HMAT_ERR_INVALID_ARG, "leading dimension smaller than n");
+    const uintptr_t xb = (uintptr_t)x, xe = (uintptr_t)(x + (nrhs - 1) * ldx + n);
+    const uintptr_t yb = (uintptr_t)y, ye = (uintptr_t)(y + (nrhs - 1) * ldy + n);
+    if (xb < ye && yb < xe) return fail(HMAT_ERR_INVALID_ARG, "x and y overlap");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+        const hipError_t e = hipSetDevice(h->device);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevPlan &p = h->plan;
+    for (int32_t c = 0; c < nrhs; ++c) {
+        const float *xc = x + c * ldx;
+        float *yc = y + c * ldy;
+        hmat_status s;
+        if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
+        int e = 0;
+        if (p.num_vtiles > 0 && (e = hmat::launch_vphase(p, xc, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("V-phase launch: ") + hipGetErrorString((hipError_t)e));
+        if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
+        if (p.num_z1 > 0 && (e = hmat::launch_zfinish(p, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("z-finish launch: ") + hipGetErrorString((hipError_t)e));
+        if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
+        if ((e = hmat::launch_uphase(p, xc, yc, alpha, beta, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("U-phase launch: ") + hipGetErrorString((hipError_t)e));
+        if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
+        if (h->timing) h->timed_calls++;
+    }
+    return HMAT_OK;
+}
+
+hmat_status hmat_set_timing(hmat_t h, int32_t enable) {
+    if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
+    if (h->events_used > 0) {
+        const hipError_t e = hipEventSynchronize(h->events[h->events_used - 1]);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    }
+    h->timing = enable != 0;
+    h->events_used = 0;
+    h->timed_calls = 0;
+    for (double &m : h->ms) m = 0.0;
+    return HMAT_OK;
+}
+
+hmat_status hmat_get_timing(hmat_t h, double ms[HMAT_NUM_PHASES], int64_t *calls) {
+    if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
+    if (!ms || !calls) return fail(HMAT_ERR_INVALID_ARG, "output pointers must not be NULL");
+    const size_t per = HMAT_NUM_PHASES + 1;
+    const size_t sets = h->events_used / per;
+    if (sets > 0) {
+        const hipError_t e = hipEventSynchronize(h->events[sets * per - 1]);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    }
+    for (size_t k = 0; k < sets; ++k)
+        for (int ph = 0; ph < HMAT_NUM_PHASES; ++ph) {
+            float t = 0.0f;
+            const hipError_t e = hipEventElapsedTime(&t, h->events[k * per + ph], h->events[k * per + ph + 1]);
+            if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+            h->ms[ph] += t;
+        }
+    h->events_used = 0;
+    for (int ph = 0; ph < HMAT_NUM_PHASES; ++ph) ms[ph] = h->ms[ph];
+    *calls = h->timed_calls;
+    return HMAT_OK;
+}
+
+hmat_status hmat_probe_bandwidth(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream) {
+    if (!src || !dst) return fail(HMAT_ERR_INVALID_ARG, "src and dst must not be NULL");
+    if (bytes <= 0 || bytes % 16 != 0) return fail(HMAT_ERR_INVALID_ARG, "bytes must be a positive multiple of 16");
+    if (mode != 0 && mode != 1) return fail(HMAT_ERR_INVALID_ARG, "mode must be 0 (read) or 1 (copy)");
+    const int e = hmat::launch_probe(src, dst, bytes, mode, stream);
+    if (e != 0) return fail(HMAT_ERR_DEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));
+    return HMAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal interface between the host side of libhmat and its HIP kernels.
+//
+// Device layout (built by hmat_create, streamed by the kernels):
+//
+//  * A "chunk" is a box at depth max(L-1, 0): the parent of a group of leaves.
+//    Chunks tile [0, n) in tree order and are the unit of device work.
+//
+//  * V panel (source side, Sec. 4.1.1, Eq. (4.2)): for chunk p, its columns are
+//    the V factors of every low-rank block whose source box contains p, level
+//    by level from the root down, and inside a level ordered by target sibling.
+//    The columns are cut into blocks of 64; one "vtile" = (chunk, column
+//    block). A vtile stores rows in vectors of VW consecutive rows (VW = 4 for
+//    FP32, 8 for FP16): element (i, 64 cb + l) sits at
+//        off + ((i / VW) * 64 + l) * VW + i % VW,
+//    so one 16-byte load per lane reads 64 columns x VW rows, 1 KiB per wave,
+//    contiguous.
+//
+//  * UD panel (target side, Sec. 4.1.5, Eqs. (4.6)-(4.8)): for chunk p, its
+//    columns are the U factors of every low-rank block whose target box
+//    contains p (same level/sibling order, matching the z layout), then the
+//    dense leaf blocks of p grouped by source leaf. Rows come in tiles of 64;
+//    element (i, j) of tile i / 64 sits at
+//        off + (i / 64) * nq * 64 * VW + ((j / VW) * 64 + i % 64) * VW + j % VW,
+//    so each lane owns one row and reads VW columns per 16-byte load. The
+//    low-rank part is padded to a multiple of VW columns, and so is each
+//    source leaf of the dense part.
+//
+//  * part: per-chunk partial sums of V^T x (one float per V column of the
+//    chunk, 64-padded). zg: per target box t, the concatenated vectors
+//    z_ts = V_ts^T x_s over its siblings s, times the block's scales.
+#pragma once
+
+#include <cstdint>
+
+namespace hmat {
+
+constexpr int kWave = 64;
+constexpr int kMaxLdsFloats = 16384;  // U-phase vector operand budget per chunk (64 KiB)
+
+struct ChunkMeta {
+    int32_t row_begin;   // first global row
+    int32_t rows;        // number of rows
+    int32_t nq;          // VW-column vectors per row of the UD panel
+    int32_t nq_lr;       // of which belong to the low-rank part
+    int64_t ud_off;      // element offset of the chunk's UD panel
+    int32_t zseg_base;   // index of its first z segment (L-1 of them)
+    int32_t dseg_base;   // index of its first dense segment (one per source leaf)
+    int32_t nleaf;       // number of leaves (dense segments)
+    int32_t dscale_base; // index of its nleaf x nleaf dense scales
+    int32_t part_base;   // offset of its partial sums
+    int32_t pad_;
+};
+
+struct ZSeg {            // a run of the U-phase vector taken from zg
+    int32_t off;
+    int32_t len;
+};
+
+struct DSeg {            // one source leaf of a chunk's dense part
+    int32_t row_begin;   // global first row of the leaf (also its x offset)
+    int32_t rows;        // |leaf|
+    int32_t nq;          // VW-column vectors it spans (padded)
+    int32_t pad_;
+};
+
+struct VTile {
+    int64_t off;         // element offset of the tile in the V panel
+    int32_t chunk;
+    int32_t pout;        // index of its 64 partial sums in part
+};
+
+struct ZItem {           // stage 1 of the partial reduction
+    int32_t chunk0;      // first chunk of the slice
+    int32_t nchunks;     // chunks in the slice
+    int32_t vcol;        // column of the block inside each chunk's partial vector
+    int32_t rank;
+    int32_t dst;         // destination offset (zg when final, else slice buffer)
+    float scale;         // applied when final (1 otherwise)
+};
+
+struct ZItem2 {          // stage 2: sum of slices of a block spanning many chunks
+    int32_t src;         // offset of its first slice in the slice buffer
+    int32_t nslices;
+    int32_t rank;
+    int32_t dst;         // offset in zg
+    float scale;
+    int32_t pad_;
+};
+
+struct DevPlan {
+    int32_t storage;          // hmat_storage
+    int32_t num_chunks;
+    int32_t num_vtiles;
+    int32_t num_z1;
+    int32_t num_z2;
+    int32_t num_levels;       // L - 1 (low-rank levels), >= 0
+    int32_t lds_floats;       // largest U-phase vector (padded)
+    int32_t max_leaf_rows;
+    const void *V;            // float or _Float16
+    const void *UD;
+    float *part;
+    float *slice;
+    float *zg;
+    const ChunkMeta *chunks;
+    const ZSeg *zsegs;
+    const DSeg *dsegs;
+    const float *dscale;
+    const VTile *vtiles;
+    const ZItem *z1;
+    const ZItem2 *z2;
+};
+
+// Kernel launchers (hmat_kernels.hip). Each returns a hipError_t as int.
+int launch_vphase(const DevPlan &p, const float *x, void *stream);
+int launch_zfinish(const DevPlan &p, void *stream);
+int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float beta,
+                  void *stream);
+int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
+
+}  // namespace hmat

@@ -1,0 +1,302 @@
+// HIP kernels (gfx950) of the single-vector H-matrix-vector product.
+//
+// One product y = alpha K x + beta y runs as four launches on the caller's
+// stream, the single-GPU form of the five steps of Sec. 4.1:
+//   k_vphase   Step 1 on the source side (Eq. (4.2)): per chunk and per block
+//              of 64 V columns, partial sums of V^T x over the chunk's rows;
+//   k_zsum1/2  Steps 2-4 (tree-reduction, source-to-target transfer and
+//              tree-broadcast) collapse to a fixed-order sum of those partials
+//              over the chunks of each source box, written straight into the
+//              target box's slot of z;
+//   k_uphase   Step 5 (Eqs. (4.6)-(4.8)): every row reads its U factors of
+//              all levels and its dense leaf row once, against z and x staged
+//              in LDS, and writes y once.
+// All streams are HBM-bound (two flops per stored element); the layouts make
+// every wave-level load a contiguous 1 KiB.
+#include <hip/hip_runtime.h>
+
+#include "hmat.h"
+#include "hmat_internal.h"
+
+namespace hmat {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int STORE>
+struct Form;
+
+template <>
+struct Form<HMAT_STORE_FP32> {
+    using Vec = f32x4;
+    using Elem = float;
+    static constexpr int VW = 4;
+    __device__ static inline void load(const Vec *p, float (&v)[VW]) {
+        const Vec t = __builtin_nontemporal_load(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+};
+
+template <>
+struct Form<HMAT_STORE_FP16_SCALED> {
+    using Vec = f16x8;
+    using Elem = _Float16;
+    static constexpr int VW = 8;
+    __device__ static inline void load(const Vec *p, float (&v)[VW]) {
+        const Vec t = __builtin_nontemporal_load(p);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = (float)t[e];
+    }
+};
+
+constexpr int kUnroll = 8;
+
+__device__ inline int wave_id_in_grid(int waves_per_block) {
+    return __builtin_amdgcn_readfirstlane((int)blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6));
+}
+
+// ---------------------------------------------------------------------------
+// V-phase: one wave per vtile; lane l owns column 64 cb + l of the chunk and
+// accumulates sum_i V[i, col] x[i] over the chunk's rows. x is uniform across
+// the wave, so its loads are scalar.
+// ---------------------------------------------------------------------------
+template <int STORE>
+__global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restrict__ x) {
+    using F = Form<STORE>;
+    constexpr int VW = F::VW;
+    const int w = wave_id_in_grid(4);
+    if (w >= p.num_vtiles) return;
+    const int lane = threadIdx.x & 63;
+    const VTile vt = p.vtiles[w];
+    const int rows = p.chunks[vt.chunk].rows;
+    const float *__restrict__ xc = x + p.chunks[vt.chunk].row_begin;
+    const typename F::Vec *tile =
+        reinterpret_cast<const typename F::Vec *>(static_cast<const typename F::Elem *>(p.V) + vt.off) + lane;
+    float acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0f;
+    const int nfull = rows / VW;
+    int q = 0;
+    for (; q + kUnroll <= nfull; q += kUnroll) {
+        float v[kUnroll][VW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) F::load(tile + (int64_t)(q + u) * kWave, v[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] = fmaf(v[u][e], xc[(q + u) * VW + e], acc[e]);
+    }
+    for (; q < nfull; ++q) {
+        float v[VW];
+        F::load(tile + (int64_t)q * kWave, v);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = fmaf(v[e], xc[q * VW + e], acc[e]);
+    }
+    if (q * VW < rows) {  // ragged last vector: rows past the chunk hold zeros in V
+        float v[VW];
+        F::load(tile + (int64_t)q * kWave, v);
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            if (q * VW + e < rows) acc[e] = fmaf(v[e], xc[q * VW + e], acc[e]);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) s += acc[e];
+    p.part[vt.pout + lane] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Partial reduction, stage 1: one wave per item; the item sums, in chunk
+// order, the partials of one block over at most 32 consecutive chunks of its
+// source box. Items of boxes that span more chunks write slices that stage 2
+// adds up, also in order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zsum1(DevPlan p) {
+    const int w = wave_id_in_grid(4);
+    if (w >= p.num_z1) return;
+    const int lane = threadIdx.x & 63;
+    const ZItem it = p.z1[w];
+    for (int k = lane; k < it.rank; k += kWave) {
+        float s = 0.0f;
+        for (int c = 0; c < it.nchunks; ++c) s += p.part[p.chunks[it.chunk0 + c].part_base + it.vcol + k];
+        p.zg[it.dst + k] = s * it.scale;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zsum2(DevPlan p) {
+    const int w = wave_id_in_grid(4);
+    if (w >= p.num_z2) return;
+    const int lane = threadIdx.x & 63;
+    const ZItem2 it = p.z2[w];
+    for (int k = lane; k < it.rank; k += kWave) {
+        float s = 0.0f;
+        for (int c = 0; c < it.nslices; ++c) s += p.zg[it.src + c * it.rank + k];
+        p.zg[it.dst + k] = s * it.scale;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// U-phase + dense near field + output: one workgroup per chunk. The chunk's
+// vector operand (its ancestors' z segments, then x over each source leaf)
+// is staged in LDS; each wave takes 64-row tiles, one row per lane, and reads
+// VW columns per 16-byte load with the operand broadcast from LDS.
+// ---------------------------------------------------------------------------
+template <int STORE>
+__device__ inline float dot_range(const typename Form<STORE>::Vec *base, const float *vec, int q0, int q1) {
+    using F = Form<STORE>;
+    constexpr int VW = F::VW;
+    float a[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) a[e] = 0.0f;
+    int q = q0;
+    for (; q + kUnroll <= q1; q += kUnroll) {
+        float v[kUnroll][VW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) F::load(base + (int64_t)(q + u) * kWave, v[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) a[e] = fmaf(v[u][e], vec[(q + u) * VW + e], a[e]);
+    }
+    for (; q < q1; ++q) {
+        float v[VW];
+        F::load(base + (int64_t)q * kWave, v);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) a[e] = fmaf(v[e], vec[q * VW + e], a[e]);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) s += a[e];
+    return s;
+}
+
+template <int STORE>
+__global__ __launch_bounds__(256) void k_uphase(DevPlan p, const float *__restrict__ x, float *__restrict__ y,
+                                                float alpha, float beta) {
+    using F = Form<STORE>;
+    constexpr int VW = F::VW;
+    extern __shared__ float vec[];
+    const int c = blockIdx.x;
+    const ChunkMeta m = p.chunks[c];
+    const int tid = threadIdx.x;
+    int pos = 0;
+    for (int l = 0; l < p.num_levels; ++l) {
+        const ZSeg zs = p.zsegs[m.zseg_base + l];
+        for (int j = tid; j < zs.len; j += 256) vec[pos + j] = p.zg[zs.off + j];
+        pos += zs.len;
+    }
+    for (int j = pos + tid; j < m.nq_lr * VW; j += 256) vec[j] = 0.0f;
+    pos = m.nq_lr * VW;
+    for (int s = 0; s < m.nleaf; ++s) {
+        const DSeg ds = p.dsegs[m.dseg_base + s];
+        for (int j = tid; j < ds.nq * VW; j += 256) vec[pos + j] = j < ds.rows ? x[ds.row_begin + j] : 0.0f;
+        pos += ds.nq * VW;
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ntile = (m.rows + kWave - 1) / kWave;
+    for (int tile = wave; tile < ntile; tile += 4) {
+        const typename F::Vec *base =
+            reinterpret_cast<const typename F::Vec *>(static_cast<const typename F::Elem *>(p.UD) + m.ud_off) +
+            (int64_t)tile * m.nq * kWave + lane;
+        const int row = tile * kWave + lane;
+        float acc = dot_range<STORE>(base, vec, 0, m.nq_lr);
+        int tleaf = 0;
+        if (STORE == HMAT_STORE_FP16_SCALED)
+            while (tleaf + 1 < m.nleaf && m.row_begin + row >= p.dsegs[m.dseg_base + tleaf + 1].row_begin) ++tleaf;
+        int q = m.nq_lr;
+        for (int s = 0; s < m.nleaf; ++s) {
+            const int nq = p.dsegs[m.dseg_base + s].nq;
+            const float part = dot_range<STORE>(base, vec, q, q + nq);
+            if (STORE == HMAT_STORE_FP16_SCALED)
+                acc = fmaf(p.dscale[m.dscale_base + tleaf * m.nleaf + s], part, acc);
+            else
+                acc += part;
+            q += nq;
+        }
+        if (row < m.rows) {
+            float *yp = y + m.row_begin + row;
+            float v = alpha * acc;
+            if (beta != 0.0f) v = fmaf(beta, *yp, v);
+            *yp = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bandwidth probe: grid-stride read (sum kept live) or copy of 16-byte vectors.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_probe_read(const f32x4 *__restrict__ src, int64_t n4, float *__restrict__ out) {
+    f32x4 acc = {0, 0, 0, 0};
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+        f32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; i < n4; i += stride) acc += src[i];
+    __shared__ float red[256];
+    red[threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy(const f32x4 *__restrict__ src, int64_t n4, f32x4 *__restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+int launch_vphase(const DevPlan &p, const float *x, void *stream) {
+    const int blocks = (p.num_vtiles + 3) / 4;
+    if (p.storage == HMAT_STORE_FP16_SCALED)
+        hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP16_SCALED>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+    else
+        hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+    return (int)hipGetLastError();
+}
+
+int launch_zfinish(const DevPlan &p, void *stream) {
+    hipLaunchKernelGGL(k_zsum1, dim3((p.num_z1 + 3) / 4), dim3(256), 0, (hipStream_t)stream, p);
+    int e = (int)hipGetLastError();
+    if (e != 0 || p.num_z2 == 0) return e;
+    hipLaunchKernelGGL(k_zsum2, dim3((p.num_z2 + 3) / 4), dim3(256), 0, (hipStream_t)stream, p);
+    return (int)hipGetLastError();
+}
+
+int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float beta, void *stream) {
+    const size_t lds = (size_t)p.lds_floats * sizeof(float);
+    if (p.storage == HMAT_STORE_FP16_SCALED)
+        hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP16_SCALED>, dim3(p.num_chunks), dim3(256), lds,
+                           (hipStream_t)stream, p, x, y, alpha, beta);
+    else
+        hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP32>, dim3(p.num_chunks), dim3(256), lds, (hipStream_t)stream, p,
+                           x, y, alpha, beta);
+    return (int)hipGetLastError();
+}
+
+int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream) {
+    const int64_t n4 = bytes / 16;
+    int64_t blocks = (n4 + 256 * 8 - 1) / (256 * 8);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    if (mode == 0)
+        hipLaunchKernelGGL(k_probe_read, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                           static_cast<const f32x4 *>(src), n4, static_cast<float *>(dst));
+    else
+        hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                           static_cast<const f32x4 *>(src), n4, static_cast<f32x4 *>(dst));
+    return (int)hipGetLastError();
+}
+
+}  // namespace hmat
