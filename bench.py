@@ -1,0 +1,236 @@
+"""Benchmark: one H-matrix-vector product per step on one MI355X.
+
+Workload (default): 2D uniform 1024 x 1024 grid in [0,1]^2 (N = 2^20), leaf 64,
+log kernel -log|x-y|/(2 pi) with unit diagonal, weak admissibility, rank-32
+factors from randomized SVD (oversampling 10) computed in an untimed setup,
+one RHS x ~ N(0,1). A step is one full y = K x on the GPU: V-phase, partial
+reduction and z routing, U-phase plus dense near field. Inputs are resident
+in HBM before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--method", default=None, help="factor method override (rsvd, random, svd)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def time_matvecs(h, xd, yd, steps, warmup, stream):
+    import torch
+
+    import paper_2008_12441_amd as hm
+
+    n = h.n
+    for _ in range(warmup):
+        hm.hmat_matvec(h.handle, 1, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
+    torch.cuda.synchronize()
+    hm.hmat_set_timing(h.handle, True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        hm.hmat_matvec(h.handle, 1, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    phase_ms, calls = hm.hmat_get_timing(h.handle)
+    hm.hmat_set_timing(h.handle, False)
+    assert calls == steps
+    return total_ms / steps, [m / steps for m in phase_ms]
+
+
+def probe_bandwidth(stream, nbytes=4 << 30, reps=5):
+    import torch
+
+    import paper_2008_12441_amd as hm
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty(65536, dtype=torch.float32, device="cuda")
+    hm.hmat_probe_bandwidth(src.data_ptr(), dst.data_ptr(), nbytes, 0, stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        hm.hmat_probe_bandwidth(src.data_ptr(), dst.data_ptr(), nbytes, 0, stream.cuda_stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    read_gbps = nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    # one copy of known size: the calibration point for hardware byte counters
+    half = nbytes // 2
+    cpy = torch.empty(half // 4, dtype=torch.float32, device="cuda")
+    t0.record(stream)
+    hm.hmat_probe_bandwidth(src.data_ptr(), cpy.data_ptr(), half, 1, stream.cuda_stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 2 * half / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst, cpy
+    torch.cuda.empty_cache()
+    return read_gbps, copy_gbps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported by this build "
+              "(the path holds the whole H-matrix on a single GPU; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2008_12441_amd as hm
+    from hmat_inputs import WORKLOADS, build_workload
+    from hmat_inputs.tree import stored_elements
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hm.load_library()
+    w = WORKLOADS[args.config]
+    stream = torch.cuda.current_stream()
+
+    read_gbps, copy_gbps = probe_bandwidth(stream)
+    log(f"probe: read {read_gbps:.0f} GB/s, copy {copy_gbps:.0f} GB/s")
+
+    t0 = time.time()
+    data, x = build_workload(args.config, device="cuda", method=args.method)
+    log(f"setup ({w.describe()}): {time.time() - t0:.1f} s")
+    n = data.n
+    t = data.tree
+    tree, blocks, keep = hm.make_descriptors(t.parent, t.begin, t.end, data.blocks.target,
+                                             data.blocks.source, data.blocks.rank, data.pool,
+                                             data.off_a, data.off_b)
+    t0 = time.time()
+    h = hm.HMatrix(tree, blocks, storage="fp32")
+    info = h.info
+    log(f"hmat_create fp32: {time.time() - t0:.1f} s, {info}")
+    xd = torch.from_numpy(np.ascontiguousarray(x[:, 0])).cuda()
+    yd = torch.empty_like(xd)
+
+    ms, phase_ms = time_matvecs(h, xd, yd, args.steps, args.warmup, stream)
+    y = yd.cpu().numpy().astype(np.float64)
+    vec_bytes = 2 * n * 4  # x read once, y written once
+    alg_bytes = info["factor_bytes"] + vec_bytes
+    gbps = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"fp32: {ms:.4f} ms/matvec, {gbps:.0f} GB/s algorithmic, phases(ms) {phase_ms}")
+
+    # dominant kernel: the U-phase (U of every level + dense near field + x + y)
+    sz = t.end - t.begin
+    is_lr = data.blocks.rank > 0
+    u_elems = int(np.sum(sz[data.blocks.target[is_lr]].astype(np.int64) * data.blocks.rank[is_lr]))
+    d_elems = int(np.sum((sz[data.blocks.target] * sz[data.blocks.source])[~is_lr]))
+    v_elems = int(np.sum(sz[data.blocks.source[is_lr]].astype(np.int64) * data.blocks.rank[is_lr]))
+    assert u_elems + d_elems + v_elems == stored_elements(t, data.blocks)
+    uphase_bytes = 4 * (u_elems + d_elems) + vec_bytes
+    vphase_bytes = 4 * v_elems + 4 * n
+    phases = {"vphase": {"ms": phase_ms[0], "alg_bytes": vphase_bytes},
+              "zfinish": {"ms": phase_ms[1]},
+              "uphase_dense": {"ms": phase_ms[2], "alg_bytes": uphase_bytes}}
+    for k in ("vphase", "uphase_dense"):
+        phases[k]["GBps"] = phases[k]["alg_bytes"] / (phases[k]["ms"] * 1e-3) / 1e9
+    dom = max(("vphase", "uphase_dense"), key=lambda k: phases[k]["ms"])
+    achieved = phases[dom]["GBps"]
+
+    out_extra = {}
+    # low-precision form on the same problem
+    if not args.no_fp16:
+        t0 = time.time()
+        h16 = hm.HMatrix(tree, blocks, storage="fp16")
+        log(f"hmat_create fp16: {time.time() - t0:.1f} s")
+        y16d = torch.empty_like(xd)
+        ms16, ph16 = time_matvecs(h16, xd, y16d, args.steps, args.warmup, stream)
+        y16 = y16d.cpu().numpy().astype(np.float64)
+        b16 = h16.info["factor_bytes"] + vec_bytes
+        out_extra["fp16_scaled"] = {"ms_per_step": ms16, "GBps": b16 / (ms16 * 1e-3) / 1e9,
+                                    "speedup_vs_fp32": ms / ms16, "phases_ms": ph16}
+        h16.close()
+        log(f"fp16: {ms16:.4f} ms/matvec, speedup {ms / ms16:.2f}x")
+    else:
+        y16 = None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        prep = oracle.prepare(data)
+        threads = oracle.max_threads()
+        oracle.oracle_matvec(prep, x)  # warm-up
+        times, ref = [], None
+        t_start = time.time()
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.oracle_matvec(prep, x)[:, 0]
+            times.append(time.perf_counter() - t0)
+            if time.time() - t_start >= args.cpu_seconds:
+                break
+        cpu_s = float(np.median(times))
+        cpu = {"value": round(alg_bytes / cpu_s / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(times)} full FP64 oracle matvecs of this workload (median {cpu_s:.3f} s each)",
+               "matvecs_per_s": round(1.0 / cpu_s, 3)}
+        rel = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+        out_extra["rel_err_vs_fp64_oracle"] = rel
+        if y16 is not None:
+            out_extra["fp16_scaled"]["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(y16 - ref) / np.linalg.norm(ref))
+        log(f"oracle: {cpu_s:.3f} s/matvec on {threads} threads; fp32 rel err {rel:.3e}")
+
+    result = {
+        "metric": "H-matvec GB/s (% HBM peak) N=2^20 r=32; low-prec/batched speedup @1e-3 err",
+        "value": round(gbps, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {w.describe()}", "n": n, "rank": w.rank, "leaf": 64,
+                   "nrhs": 1, "storage": "fp32", "factor_bytes": info["factor_bytes"],
+                   "alg_bytes_per_step": alg_bytes},
+        "pct_hbm_peak": round(100.0 * gbps / HBM_PEAK_GBPS, 2),
+        "pct_probe_read": round(100.0 * gbps / read_gbps, 2),
+        "probe_GBps": {"read": round(read_gbps, 1), "copy": round(copy_gbps, 1)},
+        "matvecs_per_s": round(1e3 / ms, 2),
+        "roofline": {"kernel": "k_uphase (U of all levels + dense near field + y)" if dom == "uphase_dense"
+                     else "k_vphase", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "alg_bytes_per_launch": phases[dom]["alg_bytes"], "avg_ms": round(phases[dom]["ms"], 5)},
+        "phases": phases,
+        "cpu_baseline": cpu,
+    }
+    result.update(out_extra)
+    h.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
