@@ -98,6 +98,23 @@ def probe_bandwidth(stream, nbytes=4 << 30, reps=5):
     return read_gbps, copy_gbps
 
 
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel source changed after the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "c2_fp32_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2008_12441_amd", "csrc", "hmat_kernels.hip")
+    try:
+        prof = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel") != kernel_key or prof.get("kernel_source_sha256_16") != digest:
+        return None
+    return int(prof["traffic_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,7 +239,9 @@ def main():
         "matvecs_per_s": round(1e3 / ms, 2),
         "roofline": {"kernel": "k_uphase (U of all levels + dense near field + y)" if dom == "uphase_dense"
                      else "k_vphase", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_from_profile("k_uphase<FP32>") if (dom == "uphase_dense" and args.config == "c2")
+                     else None,
                      "alg_bytes_per_launch": phases[dom]["alg_bytes"], "avg_ms": round(phases[dom]["ms"], 5)},
         "phases": phases,
         "cpu_baseline": cpu,
