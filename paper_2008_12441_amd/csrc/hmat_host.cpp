@@ -734,6 +734,11 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     p.zg = static_cast<float *>(ws);
     p.slice = p.zg + hp.zg_floats;
     if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
+    {
+        std::vector<int32_t> pb(hp.chunks.size());
+        for (size_t c = 0; c < pb.size(); ++c) pb[c] = hp.chunks[c].part_base;
+        if ((s = upload(h, pb, &p.pbase)) != HMAT_OK) return s;
+    }
     if ((s = upload(h, hp.zsegs, &p.zsegs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.dsegs, &p.dsegs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.dscale, &p.dscale)) != HMAT_OK) return s;

@@ -102,6 +102,7 @@ struct DevPlan {
     float *slice;
     float *zg;
     const ChunkMeta *chunks;
+    const int32_t *pbase;     // per chunk: offset of its partial sums (= chunks[c].part_base)
     const ZSeg *zsegs;
     const DSeg *dsegs;
     const float *dscale;

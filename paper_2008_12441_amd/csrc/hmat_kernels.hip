@@ -50,7 +50,14 @@ struct Form<HMAT_STORE_FP16_SCALED> {
     }
 };
 
-constexpr int kUnroll = 8;
+#ifndef HMAT_VUNROLL
+#define HMAT_VUNROLL 8
+#endif
+#ifndef HMAT_UUNROLL
+#define HMAT_UUNROLL 8
+#endif
+constexpr int kVUnroll = HMAT_VUNROLL;  // 16-byte loads in flight per lane, V-phase
+constexpr int kUUnroll = HMAT_UUNROLL;  // same for the U-phase
 
 __device__ inline int wave_id_in_grid(int waves_per_block) {
     return __builtin_amdgcn_readfirstlane((int)blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6));
@@ -78,12 +85,12 @@ __global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restri
     for (int e = 0; e < VW; ++e) acc[e] = 0.0f;
     const int nfull = rows / VW;
     int q = 0;
-    for (; q + kUnroll <= nfull; q += kUnroll) {
-        float v[kUnroll][VW];
+    for (; q + kVUnroll <= nfull; q += kVUnroll) {
+        float v[kVUnroll][VW];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) F::load(tile + (int64_t)(q + u) * kWave, v[u]);
+        for (int u = 0; u < kVUnroll; ++u) F::load(tile + (int64_t)(q + u) * kWave, v[u]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < kVUnroll; ++u)
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] = fmaf(v[u][e], xc[(q + u) * VW + e], acc[e]);
     }
@@ -117,9 +124,19 @@ __global__ __launch_bounds__(256) void k_zsum1(DevPlan p) {
     if (w >= p.num_z1) return;
     const int lane = threadIdx.x & 63;
     const ZItem it = p.z1[w];
+    const int32_t *pb = p.pbase + it.chunk0;
     for (int k = lane; k < it.rank; k += kWave) {
-        float s = 0.0f;
-        for (int c = 0; c < it.nchunks; ++c) s += p.part[p.chunks[it.chunk0 + c].part_base + it.vcol + k];
+        // eight independent partial sums keep eight loads in flight; they are
+        // combined in a fixed order, so the result stays deterministic
+        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const float *src = p.part + it.vcol + k;
+        int c = 0;
+        for (; c + 8 <= it.nchunks; c += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += src[pb[c + u]];
+        }
+        for (; c < it.nchunks; ++c) a[0] += src[pb[c]];
+        const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         p.zg[it.dst + k] = s * it.scale;
     }
 }
@@ -130,8 +147,15 @@ __global__ __launch_bounds__(256) void k_zsum2(DevPlan p) {
     const int lane = threadIdx.x & 63;
     const ZItem2 it = p.z2[w];
     for (int k = lane; k < it.rank; k += kWave) {
-        float s = 0.0f;
-        for (int c = 0; c < it.nslices; ++c) s += p.zg[it.src + c * it.rank + k];
+        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const float *src = p.zg + it.src + k;
+        int c = 0;
+        for (; c + 8 <= it.nslices; c += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += src[(c + u) * it.rank];
+        }
+        for (; c < it.nslices; ++c) a[0] += src[c * it.rank];
+        const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         p.zg[it.dst + k] = s * it.scale;
     }
 }
@@ -150,12 +174,12 @@ __device__ inline float dot_range(const typename Form<STORE>::Vec *base, const f
 #pragma unroll
     for (int e = 0; e < VW; ++e) a[e] = 0.0f;
     int q = q0;
-    for (; q + kUnroll <= q1; q += kUnroll) {
-        float v[kUnroll][VW];
+    for (; q + kUUnroll <= q1; q += kUUnroll) {
+        float v[kUUnroll][VW];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) F::load(base + (int64_t)(q + u) * kWave, v[u]);
+        for (int u = 0; u < kUUnroll; ++u) F::load(base + (int64_t)(q + u) * kWave, v[u]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < kUUnroll; ++u)
 #pragma unroll
             for (int e = 0; e < VW; ++e) a[e] = fmaf(v[u][e], vec[(q + u) * VW + e], a[e]);
     }
