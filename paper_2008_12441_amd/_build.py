@@ -32,12 +32,15 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
     host_o = os.path.join(BUILD, "hmat_host.o")
     kern_o = os.path.join(BUILD, "hmat_kernels.o")
+    mr_o = os.path.join(BUILD, "hmat_mr_kernels.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "hmat_host.cpp"), "-o", host_o], verbose)
     _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, "hmat_kernels.hip"),
           "-o", kern_o], verbose)
+    _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, "hmat_mr_kernels.hip"),
+          "-o", mr_o], verbose)
     tmp = LIB + ".tmp"
     _run([os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o,
-          kern_o, "-o", tmp, "-lpthread"], verbose)
+          kern_o, mr_o, "-o", tmp, "-lpthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

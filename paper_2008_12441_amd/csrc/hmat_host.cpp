@@ -31,7 +31,9 @@ struct hmat_handle {
     int32_t storage = 0;
     int32_t max_nrhs = 1;
     hmat_info info{};
+    bool mr = false;               // multi-RHS (MFMA) layout
     DevPlan plan{};
+    hmat::DevPlanMR mrp{};
     std::vector<void *> dev_allocs;
     // phase timing
     bool timing = false;
@@ -600,6 +602,313 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
     });
 }
 
+
+// ---------------------------------------------------------------------------
+// Multi-RHS (MFMA) layout.
+// ---------------------------------------------------------------------------
+constexpr int32_t kUnitChunks = 16;   // chunks a V-phase unit accumulates over
+constexpr int32_t kMaxRankMR = 128;
+
+struct HostPlanMR {
+    int32_t kb = 16, vw = 4, ntmax = 1;
+    int32_t chunk_depth = 0;
+    std::vector<int32_t> chunk_node;
+    std::vector<int32_t> anc;                  // chunk x (chunk_depth + 1)
+    std::vector<hmat::MRChunk> chunks;
+    std::vector<hmat::MRLeaf> leaves;
+    std::vector<int32_t> leaf_node;            // node id of each leaf entry
+    std::vector<hmat::MRVUnit> vunits;
+    std::vector<int32_t> unit_node, unit_group;
+    std::vector<hmat::MRZItem> zitems;
+    std::vector<int64_t> zitem_block;
+    std::vector<hmat::MRSeg> segs;
+    std::vector<int64_t> seg_block;            // low-rank block of a z segment, or -1
+    std::vector<int32_t> seg_node;             // source leaf node of an x segment
+    std::vector<hmat::MRTile> tiles;
+    std::vector<float> dscale;
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> colmap;  // per node s: V column -> (block, j)
+    std::vector<float> sU, sV, sD;
+    int64_t v_frags = 0, ud_frags = 0, x_frags = 0, z_frags = 0, part_floats = 0;
+};
+
+hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
+                          int32_t storage, int32_t max_nrhs, HostPlanMR &hp) {
+    const bool f16 = storage == HMAT_STORE_FP16_SCALED;
+    hp.kb = f16 ? 32 : 16;
+    hp.vw = f16 ? 8 : 4;
+    hp.ntmax = (std::min(max_nrhs, 128) + 15) / 16;
+    const int32_t KB = hp.kb, L = t.L, cd = std::max(L - 1, 0);
+    hp.chunk_depth = cd;
+    for (int64_t b = 0; b < nb; ++b)
+        if (bl[b].rank > kMaxRankMR)
+            return fail(HMAT_ERR_UNSUPPORTED, "multi-RHS handles support ranks up to 128");
+    for (int32_t i = 0; i < t.num_nodes; ++i)
+        if (t.depth[i] == cd) hp.chunk_node.push_back(i);
+    std::sort(hp.chunk_node.begin(), hp.chunk_node.end(),
+              [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
+    const int32_t nc = (int32_t)hp.chunk_node.size();
+    hp.anc.assign((size_t)nc * (cd + 1), 0);
+    std::vector<int32_t> cfirst(t.num_nodes, INT32_MAX), clast(t.num_nodes, -1);
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t a = hp.chunk_node[c];
+        for (int32_t d = cd; d >= 0; --d) {
+            hp.anc[(size_t)c * (cd + 1) + d] = a;
+            cfirst[a] = std::min(cfirst[a], c);
+            clast[a] = std::max(clast[a], c + 1);
+            a = t.parent[a];
+        }
+    }
+    hp.sU.assign(nb, 1.0f);
+    hp.sV.assign(nb, 1.0f);
+    hp.sD.assign(nb, 1.0f);
+    if (f16) {
+        std::atomic<bool> ok{true};
+        parallel_for(nb, [&](int64_t b) {
+            bool fin = true;
+            const hmat_block_desc &d = bl[b];
+            const int64_t mt = t.size(d.target), ms = t.size(d.source);
+            if (d.rank == 0) {
+                hp.sD[b] = pow2_scale_f16(col_major_amax(d.a, mt, ms, d.lda, &fin));
+            } else {
+                hp.sU[b] = pow2_scale_f16(col_major_amax(d.a, mt, d.rank, d.lda, &fin));
+                hp.sV[b] = pow2_scale_f16(col_major_amax(d.b, ms, d.rank, d.ldb, &fin));
+            }
+            if (!fin) ok = false;
+        });
+        if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
+    }
+    // chunks and their leaves (K-block aligned)
+    int64_t xf = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t node = hp.chunk_node[c];
+        hmat::MRChunk m{};
+        m.row_begin = (int32_t)t.begin[node];
+        m.rows = (int32_t)t.size(node);
+        m.leaf_base = (int32_t)hp.leaves.size();
+        std::vector<int32_t> lv;
+        if (L == 0) lv.push_back(node);
+        else
+            for (int32_t j = 0; j < t.nkids(node); ++j) lv.push_back(t.kid(node, j));
+        m.nleaf = (int32_t)lv.size();
+        int32_t kb = 0;
+        for (int32_t lf : lv) {
+            hmat::MRLeaf e{(int32_t)t.begin[lf], (int32_t)t.size(lf), kb, (int32_t)((t.size(lf) + KB - 1) / KB)};
+            kb += e.nkb;
+            hp.leaves.push_back(e);
+            hp.leaf_node.push_back(lf);
+        }
+        m.nkb = kb;
+        m.xoff = xf;
+        xf += (int64_t)kb * hp.ntmax;
+        m.dscale_base = (int32_t)hp.dscale.size();
+        for (int32_t it = 0; it < m.nleaf; ++it)
+            for (int32_t is = 0; is < m.nleaf; ++is)
+                hp.dscale.push_back(L == 0 ? hp.sD[0] : hp.sD[st.block_of(t, lv[it], lv[is])]);
+        hp.chunks.push_back(m);
+    }
+    hp.x_frags = xf;
+    // V units: per level-l source box s and 64-column group, at most kUnitChunks chunks each
+    hp.colmap.assign(t.num_nodes, {});
+    std::vector<int32_t> ubase(t.num_nodes, -1), nunit(t.num_nodes, 0), vcol(nb, -1);
+    int64_t af = 0;
+    for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+        std::vector<int32_t> boxes;
+        for (int32_t i = 0; i < t.num_nodes; ++i)
+            if (t.depth[i] == lvl) boxes.push_back(i);
+        std::sort(boxes.begin(), boxes.end(), [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
+        for (int32_t s : boxes) {
+            const int32_t p = t.parent[s];
+            auto &cm = hp.colmap[s];
+            for (int32_t j = 0; j < t.nkids(p); ++j) {
+                const int32_t tt = t.kid(p, j);
+                if (tt == s) continue;
+                const int64_t b = st.block_of(t, tt, s);
+                vcol[b] = (int32_t)cm.size();
+                for (int32_t k = 0; k < bl[b].rank; ++k) cm.emplace_back(b, k);
+            }
+            const int32_t W = (int32_t)cm.size();
+            const int32_t ngroups = (W + 63) / 64;
+            const int32_t c0 = cfirst[s], c1 = clast[s];
+            const int32_t nu = (c1 - c0 + kUnitChunks - 1) / kUnitChunks;
+            ubase[s] = (int32_t)hp.vunits.size();
+            nunit[s] = nu;
+            for (int32_t g = 0; g < ngroups; ++g) {
+                const int32_t nm = std::min(4, (W - 64 * g + 15) / 16);
+                for (int32_t i = 0; i < nu; ++i) {
+                    hmat::MRVUnit u{};
+                    u.aoff = af;
+                    u.c0 = c0 + i * kUnitChunks;
+                    u.nc = std::min(kUnitChunks, c1 - u.c0);
+                    u.nm = nm;
+                    u.poff = (int64_t)hp.vunits.size() * 64 * hp.ntmax * 16;
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) af += (int64_t)hp.chunks[c].nkb * nm;
+                    hp.vunits.push_back(u);
+                    hp.unit_node.push_back(s);
+                    hp.unit_group.push_back(g);
+                }
+            }
+        }
+    }
+    hp.v_frags = af;
+    hp.part_floats = (int64_t)hp.vunits.size() * 64 * hp.ntmax * 16;
+    // z items: one per low-rank block
+    std::vector<int32_t> zitem_of(nb, -1);
+    int64_t zf = 0;
+    for (int64_t b = 0; b < nb && L >= 2; ++b) {
+        if (bl[b].rank == 0) continue;
+        const int32_t s = bl[b].source;
+        hmat::MRZItem z{};
+        z.ubase = ubase[s];
+        z.nu = nunit[s];
+        z.vcol = vcol[b];
+        z.rank = bl[b].rank;
+        z.scale = hp.sU[b] * hp.sV[b];
+        z.zoff = zf;
+        zf += (int64_t)((bl[b].rank + KB - 1) / KB) * hp.ntmax;
+        zitem_of[b] = (int32_t)hp.zitems.size();
+        hp.zitems.push_back(z);
+        hp.zitem_block.push_back(b);
+    }
+    hp.z_frags = zf;
+    // U-phase segments per chunk, and row tiles per target leaf
+    int64_t uf = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        hmat::MRChunk &m = hp.chunks[c];
+        m.seg_base = (int32_t)hp.segs.size();
+        int32_t seg_kb = 0;
+        for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
+            const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
+            const int32_t p = t.parent[a];
+            for (int32_t j = 0; j < t.nkids(p); ++j) {
+                const int32_t s = t.kid(p, j);
+                if (s == a) continue;
+                const int64_t b = st.block_of(t, a, s);
+                const hmat::MRZItem &z = hp.zitems[zitem_of[b]];
+                hmat::MRSeg sg{z.zoff, (bl[b].rank + KB - 1) / KB, 0, zitem_of[b], 0};
+                seg_kb += sg.nkb;
+                hp.segs.push_back(sg);
+                hp.seg_block.push_back(b);
+                hp.seg_node.push_back(-1);
+            }
+        }
+        for (int32_t lf = 0; lf < m.nleaf; ++lf) {
+            const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
+            hmat::MRSeg sg{m.xoff + (int64_t)e.kb0 * hp.ntmax, e.nkb, 1, c, lf};
+            seg_kb += sg.nkb;
+            hp.segs.push_back(sg);
+            hp.seg_block.push_back(-1);
+            hp.seg_node.push_back(hp.leaf_node[m.leaf_base + lf]);
+        }
+        m.nseg = (int32_t)hp.segs.size() - m.seg_base;
+        for (int32_t lf = 0; lf < m.nleaf; ++lf) {
+            const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
+            for (int32_t r0 = 0; r0 < e.rows; r0 += 64) {
+                hmat::MRTile tl{};
+                tl.aoff = uf;
+                tl.chunk = c;
+                tl.row0 = e.row_begin + r0;
+                tl.rows = std::min(64, e.rows - r0);
+                tl.nm = (tl.rows + 15) / 16;
+                tl.tleaf = lf;
+                uf += (int64_t)seg_kb * tl.nm;
+                hp.tiles.push_back(tl);
+            }
+        }
+    }
+    hp.ud_frags = uf;
+    return HMAT_OK;
+}
+
+// Position of padded row pr of chunk c: global row, or -1 for padding.
+inline int32_t mr_row(const HostPlanMR &hp, const hmat::MRChunk &m, int32_t pr) {
+    const int32_t kb = pr / hp.kb;
+    int32_t lf = 0;
+    while (lf + 1 < m.nleaf && hp.leaves[m.leaf_base + lf + 1].kb0 <= kb) ++lf;
+    const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
+    const int32_t o = pr - e.kb0 * hp.kb;
+    return o < e.rows ? e.row_begin + o : -1;
+}
+
+template <class T>
+inline T quant(float v, float scale) {
+    if constexpr (sizeof(T) == 4) {
+        (void)scale;
+        return v;
+    } else {
+        return f32_to_f16_rne(v / scale);
+    }
+}
+
+template <class T>
+void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T *out) {
+    const int32_t vw = hp.vw, KB = hp.kb;
+    parallel_for((int64_t)hp.vunits.size(), [&](int64_t ui) {
+        const hmat::MRVUnit &u = hp.vunits[ui];
+        const int32_t s = hp.unit_node[ui], g = hp.unit_group[ui];
+        const auto &cm = hp.colmap[s];
+        int64_t af = u.aoff;
+        for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) {
+            const hmat::MRChunk &m = hp.chunks[c];
+            for (int32_t kb = 0; kb < m.nkb; ++kb)
+                for (int32_t ms = 0; ms < u.nm; ++ms) {
+                    T *fr = out + (af + (int64_t)kb * u.nm + ms) * 64 * vw;
+                    for (int32_t l = 0; l < 64; ++l) {
+                        const int32_t col = 64 * g + 16 * ms + l % 16;
+                        for (int32_t e = 0; e < vw; ++e) {
+                            const int32_t pr = kb * KB + vw * (l / 16) + e;
+                            const int32_t gr = mr_row(hp, m, pr);
+                            float v = 0.0f, sc = 1.0f;
+                            if (gr >= 0 && col < (int32_t)cm.size()) {
+                                const int64_t b = cm[col].first;
+                                const hmat_block_desc &d = bl[b];
+                                v = d.b[(gr - t.begin[s]) + (int64_t)cm[col].second * d.ldb];
+                                sc = hp.sV[b];
+                            }
+                            fr[l * vw + e] = quant<T>(v, sc);
+                        }
+                    }
+                }
+            af += (int64_t)m.nkb * u.nm;
+        }
+    });
+}
+
+template <class T>
+void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, const HostPlanMR &hp, T *out) {
+    const int32_t vw = hp.vw, KB = hp.kb;
+    parallel_for((int64_t)hp.tiles.size(), [&](int64_t ti) {
+        const hmat::MRTile &tl = hp.tiles[ti];
+        const hmat::MRChunk &m = hp.chunks[tl.chunk];
+        const int32_t tnode = hp.leaf_node[m.leaf_base + tl.tleaf];
+        int64_t af = tl.aoff;
+        for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
+            const hmat::MRSeg &sg = hp.segs[si];
+            const int64_t lb = hp.seg_block[si];
+            int64_t db = -1;
+            if (sg.kind == 1) db = (t.L == 0) ? 0 : st.block_of(t, tnode, hp.seg_node[si]);
+            const hmat_block_desc &d = bl[sg.kind == 0 ? lb : db];
+            const int32_t ncols = sg.kind == 0 ? d.rank : (int32_t)t.size(hp.seg_node[si]);
+            const int32_t rbase = (int32_t)(sg.kind == 0 ? t.begin[d.target] : t.begin[tnode]);
+            const float sc = sg.kind == 0 ? hp.sU[lb] : hp.sD[db];
+            for (int32_t kb = 0; kb < sg.nkb; ++kb)
+                for (int32_t ms = 0; ms < tl.nm; ++ms) {
+                    T *fr = out + (af + (int64_t)kb * tl.nm + ms) * 64 * vw;
+                    for (int32_t l = 0; l < 64; ++l) {
+                        const int32_t tr = 16 * ms + l % 16;
+                        for (int32_t e = 0; e < vw; ++e) {
+                            const int32_t kk = kb * KB + vw * (l / 16) + e;
+                            float v = 0.0f;
+                            if (tr < tl.rows && kk < ncols)
+                                v = d.a[(tl.row0 + tr - rbase) + (int64_t)kk * d.lda];
+                            fr[l * vw + e] = quant<T>(v, sc);
+                        }
+                    }
+                }
+            af += (int64_t)sg.nkb * tl.nm;
+        }
+    });
+}
+
 void release(hmat_handle *h) {
     if (!h) return;
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
@@ -671,6 +980,64 @@ hmat_status upload_panels(hmat_handle *h, const Tree &t, const Structure &st,
     return HMAT_OK;
 }
 
+
+template <class T>
+hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const hmat_block_desc *bl,
+                      const HostPlanMR &hp) {
+    hmat::DevPlanMR &p = h->mrp;
+    const size_t frag = (size_t)64 * hp.vw * sizeof(T);  // A fragment bytes (1 KiB)
+    const size_t bfrag = hp.kb == 32 ? 2048 : 1024;      // B fragment bytes
+    void *q = nullptr;
+    hmat_status s;
+    if ((s = dev_alloc(h, hp.x_frags * bfrag, &q)) != HMAT_OK) return s;
+    p.xpack = q;
+    if ((s = dev_alloc(h, hp.z_frags * bfrag, &q)) != HMAT_OK) return s;
+    p.zpack = q;
+    if ((s = dev_alloc(h, hp.part_floats * 4, &q)) != HMAT_OK) return s;
+    p.part = static_cast<float *>(q);
+    if ((s = dev_alloc(h, hp.chunks.size() * hp.ntmax * 16 * 4, &q)) != HMAT_OK) return s;
+    p.sx = static_cast<float *>(q);
+    if ((s = dev_alloc(h, hp.zitems.size() * hp.ntmax * 16 * 4, &q)) != HMAT_OK) return s;
+    p.sz = static_cast<float *>(q);
+    if ((s = upload(h, hp.dscale, &p.dscale)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.leaves, &p.leaves)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.vunits, &p.vunits)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.zitems, &p.zitems)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
+    void *vdev = nullptr, *uddev = nullptr;
+    if ((s = dev_alloc(h, hp.v_frags * frag, &vdev)) != HMAT_OK) return s;
+    if ((s = dev_alloc(h, hp.ud_frags * frag, &uddev)) != HMAT_OK) return s;
+    try {
+        if (hp.v_frags > 0) {
+            std::vector<T> stage((size_t)hp.v_frags * 64 * hp.vw);
+            fill_v_mr<T>(t, bl, hp, stage.data());
+            const hipError_t e = hipMemcpy(vdev, stage.data(), stage.size() * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        std::vector<T> stage((size_t)hp.ud_frags * 64 * hp.vw);
+        fill_ud_mr<T>(t, st, bl, hp, stage.data());
+        const hipError_t e = hipMemcpy(uddev, stage.data(), stage.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    } catch (const std::bad_alloc &) {
+        return fail(HMAT_ERR_NOMEM, "host staging allocation failed");
+    }
+    p.V = vdev;
+    p.UD = uddev;
+    p.storage = h->storage;
+    p.ntmax = hp.ntmax;
+    p.num_chunks = (int32_t)hp.chunks.size();
+    p.num_vunits = (int32_t)hp.vunits.size();
+    p.num_zitems = (int32_t)hp.zitems.size();
+    p.num_tiles = (int32_t)hp.tiles.size();
+    h->info.device_factor_bytes = (hp.v_frags + hp.ud_frags) * (int64_t)frag;
+    h->info.workspace_bytes = (hp.x_frags + hp.z_frags) * (int64_t)bfrag + hp.part_floats * 4 +
+                              (int64_t)(hp.chunks.size() + hp.zitems.size()) * hp.ntmax * 64;
+    h->info.num_chunks = (int32_t)hp.chunks.size();
+    return HMAT_OK;
+}
+
 hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t nb,
                         const hmat_options *opts, hmat_handle *h) {
     if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
@@ -686,7 +1053,10 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     s = validate_blocks(t, blocks, nb, st);
     if (s != HMAT_OK) return s;
     HostPlan hp;
-    s = build_plan(t, st, blocks, nb, opts->storage, hp);
+    HostPlanMR hpm;
+    h->mr = opts->max_nrhs > 1;
+    s = h->mr ? build_plan_mr(t, st, blocks, nb, opts->storage, opts->max_nrhs, hpm)
+              : build_plan(t, st, blocks, nb, opts->storage, hp);
     if (s != HMAT_OK) return s;
 
     h->device = opts->device;
@@ -716,6 +1086,11 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * 4;
     in.storage = opts->storage;
     in.max_nrhs = opts->max_nrhs;
+
+    if (h->mr) {
+        if (opts->storage == HMAT_STORE_FP16_SCALED) return upload_mr<uint16_t>(h, t, st, blocks, hpm);
+        return upload_mr<float>(h, t, st, blocks, hpm);
+    }
 
     DevPlan &p = h->plan;
     p.storage = opts->storage;
@@ -829,6 +1204,17 @@ static hmat_status record_event(hmat_handle *h, hipStream_t stream) {
     return HMAT_OK;
 }
 
+struct MarkCtx {
+    hmat_handle *h;
+    hipStream_t st;
+    hmat_status err;
+};
+
+static void mark_phase(void *ctx, int) {
+    MarkCtx *m = static_cast<MarkCtx *>(ctx);
+    if (m->err == HMAT_OK) m->err = record_event(m->h, m->st);
+}
+
 hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
                         float *y, int64_t ldy, void *stream) {
     if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
@@ -845,6 +1231,18 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int
         if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (h->mr) {
+        for (int32_t c0 = 0; c0 < nrhs; c0 += 128) {
+            const int32_t kk = std::min<int32_t>(128, nrhs - c0);
+            MarkCtx mc{h, st, HMAT_OK};
+            const int e = hmat::launch_mr(h->mrp, kk, alpha, x + c0 * ldx, ldx, beta, y + c0 * ldy, ldy, st,
+                                          h->timing ? mark_phase : nullptr, &mc);
+            if (mc.err != HMAT_OK) return mc.err;
+            if (e != 0) return fail(HMAT_ERR_DEVICE, std::string("multi-RHS launch: ") + hipGetErrorString((hipError_t)e));
+            if (h->timing) h->timed_calls++;
+        }
+        return HMAT_OK;
+    }
     const DevPlan &p = h->plan;
     for (int32_t c = 0; c < nrhs; ++c) {
         const float *xc = x + c * ldx;

@@ -111,11 +111,116 @@ struct DevPlan {
     const ZItem2 *z2;
 };
 
+// ---------------------------------------------------------------------------
+// Multi-RHS layout (handles created with max_nrhs > 1): the products become
+// matrix-matrix products on MFMA tiles of 16 x 16 outputs.
+//
+//  * Fragments: an A fragment is 16 rows x KB inner indices, stored as 64
+//    lanes x 16 bytes (1 KiB): lane l holds row l % 16 and the VW consecutive
+//    inner indices VW * (l / 16) + [0, VW) of that row (FP32: KB = 16, VW = 4,
+//    fed to four 16x16x4 steps; FP16: KB = 32, VW = 8, one 16x16x32 step).
+//    A B fragment is KB inner indices x 16 columns with the mirrored lane
+//    mapping (lane l: column l % 16, inner indices VW * (l / 16) + [0, VW)),
+//    1 KiB for FP32, 2 KiB for FP16 (a high and a low half-precision part).
+//  * Rows of every chunk are padded leaf by leaf to multiples of KB, so each
+//    leaf starts on a K-block boundary.
+//  * V panel: per unit (level, source box, 64-column group, up to 16 chunks of
+//    that box) the A fragments [chunk][K-block][m-subtile]; a wave computes
+//    the unit's V^T X and writes its partial sums (64 x 16 NT floats).
+//  * Xpack: per chunk the B fragments [K-block][n-tile] of X (FP16: hi/lo
+//    with one power-of-two scale per chunk and column).
+//  * Zpack: per low-rank block the B fragments [K-block][n-tile] of its z
+//    (FP16: hi/lo, one power-of-two scale per block and column).
+//  * UD panel: per row tile (<= 64 rows of one target leaf) the A fragments
+//    [K-block over its segments][m-subtile]; segments are the z of every
+//    ancestor-level block, then x over each source leaf.
+// ---------------------------------------------------------------------------
+struct MRChunk {
+    int32_t row_begin;
+    int32_t rows;
+    int32_t nkb;          // K-blocks of its leaf-padded rows
+    int32_t leaf_base;    // first entry in the leaf table
+    int32_t nleaf;
+    int32_t seg_base;     // first U-phase segment
+    int32_t nseg;
+    int32_t dscale_base;  // nleaf x nleaf dense-block scales
+    int64_t xoff;         // first B fragment of its Xpack
+};
+
+struct MRLeaf {
+    int32_t row_begin;    // global first row
+    int32_t rows;
+    int32_t kb0;          // first K-block inside the chunk's padded rows
+    int32_t nkb;
+};
+
+struct MRVUnit {
+    int64_t aoff;         // first A fragment in the V panel
+    int32_t c0;           // first chunk
+    int32_t nc;           // chunks
+    int32_t nm;           // m-subtiles (16 columns each), 1..4
+    int32_t pad_;
+    int64_t poff;         // offset of its partial sums (floats)
+};
+
+struct MRZItem {          // one low-rank block (t, s)
+    int32_t ubase;        // unit of column group 0 of (level, s)
+    int32_t nu;           // units per column group
+    int32_t vcol;         // first column of the block among the columns of (level, s)
+    int32_t rank;
+    float scale;          // product of the U and V scales
+    int32_t pad_;
+    int64_t zoff;         // first B fragment of its Zpack
+};
+
+struct MRSeg {
+    int64_t src;          // first B fragment (Zpack or Xpack)
+    int32_t nkb;          // K-blocks
+    int32_t kind;         // 0: z of a block, 1: x over a source leaf
+    int32_t sidx;         // block id (z) or chunk id (x): scale row
+    int32_t leaf;         // source leaf index in the chunk (x)
+};
+
+struct MRTile {
+    int64_t aoff;         // first A fragment in the UD panel
+    int32_t chunk;
+    int32_t row0;         // global first row
+    int32_t rows;         // valid rows (<= 64)
+    int32_t nm;           // m-subtiles
+    int32_t tleaf;        // target leaf index in the chunk
+    int32_t pad_;
+};
+
+struct DevPlanMR {
+    int32_t storage;
+    int32_t ntmax;            // n-tiles of 16 columns allocated (max_nrhs / 16, rounded up)
+    int32_t num_chunks;
+    int32_t num_vunits;
+    int32_t num_zitems;
+    int32_t num_tiles;
+    const void *V;            // A fragments
+    const void *UD;
+    void *xpack;              // B fragments
+    void *zpack;
+    float *part;              // unit partial sums
+    float *sx;                // per chunk x 16 NT column scales of Xpack
+    float *sz;                // per block x 16 NT column scales of Zpack
+    const float *dscale;
+    const MRChunk *chunks;
+    const MRLeaf *leaves;
+    const MRVUnit *vunits;
+    const MRZItem *zitems;
+    const MRSeg *segs;
+    const MRTile *tiles;
+};
+
 // Kernel launchers (hmat_kernels.hip). Each returns a hipError_t as int.
 int launch_vphase(const DevPlan &p, const float *x, void *stream);
 int launch_zfinish(const DevPlan &p, void *stream);
 int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float beta,
                   void *stream);
 int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
+int launch_mr(const DevPlanMR &p, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
+              float *y, int64_t ldy, void *stream, void (*mark)(void *ctx, int phase), void *ctx);
 
 }  // namespace hmat

@@ -52,10 +52,21 @@ UNIFORM = [
 def test_uniform_fp32(name, d, n, r, method, kind):
     _log(f"case {name}")
     data = make_hmatrix(uniform_tree(d, n), r, kind=kind, method=method, seed=5)
-    x = make_rhs(data.n, 2, 17)
+    x = make_rhs(data.n, 1, 17)
     ref = oracle.oracle_matvec(data, x)
-    with create(data, max_nrhs=2) as h:
+    with create(data, max_nrhs=1) as h:      # single-RHS layout and kernels
         y = gpu_matvec(h, x)
+    assert_close(y, ref, FP32_TOL, ELEM_TOL)
+
+
+def test_single_rhs_alpha_beta_leading_dimension():
+    _log("case single-rhs alpha/beta")
+    data = make_hmatrix(uniform_tree(2, 64), 16, method="random", seed=4)
+    x = make_rhs(data.n, 1, 8)
+    y0 = np.random.default_rng(0).standard_normal((data.n, 1))
+    ref = oracle.oracle_matvec(data, x, alpha=-0.5, beta=2.0, y_in=y0.astype(np.float32))
+    with create(data, max_nrhs=1) as h:
+        y = gpu_matvec(h, x, alpha=-0.5, beta=2.0, y0=y0, ld_pad=5)
     assert_close(y, ref, FP32_TOL, ELEM_TOL)
 
 
@@ -153,3 +164,79 @@ def test_c2_full_size_fp16(c2_random):
     with create(data, storage="fp16") as h:
         y = gpu_matvec(h, x)
     assert_close(y, ref_dq, FP32_TOL, ELEM_TOL)
+
+
+# ---------------------------------------------------------------------------
+# Multi-RHS handles (max_nrhs > 1): the MFMA layout and kernels.
+# ---------------------------------------------------------------------------
+MR_CASES = [
+    ("c1-2d-n64-r16-svd-k3", (64, 64), 16, "svd", 3),
+    ("2d-n128-r8-random-k17", (128, 128), 8, "random", 17),
+    ("3d-n32-r16-random-k64", (32, 32, 32), 16, "random", 64),
+    ("3d-n16-r8-random-k5", (16, 16, 16), 8, "random", 5),
+    ("ragged-40x23-r8-k5", (40, 23), 8, "random", 5),
+    ("ragged-17x33x9-r8-k16", (17, 33, 9), 8, "random", 16),
+    ("ragged-255x130-r32-k33", (255, 130), 32, "random", 33),
+    ("2d-n8-L0-k2", (8, 8), 4, "random", 2),
+    ("2d-n16-L1-k2", (16, 16), 4, "random", 2),
+]
+
+
+def _tree_for(shape):
+    full = tuple(max(256 if len(shape) == 2 else 64, s) for s in shape)
+    return build_tree(shape, n_full=full)
+
+
+@pytest.mark.parametrize("name,shape,r,method,k", MR_CASES, ids=[c[0] for c in MR_CASES])
+@pytest.mark.parametrize("form", ["fp32", "fp16"])
+def test_multi_rhs(name, shape, r, method, k, form):
+    _log(f"case multi-rhs {name} {form}")
+    kind = "log" if len(shape) == 2 else "inv"
+    data = make_hmatrix(_tree_for(shape), r, kind=kind, method=method, seed=31)
+    x = make_rhs(data.n, k, 41)
+    ref_data = dequantised(data, form)
+    ref = oracle.oracle_matvec(ref_data, x)
+    with create(data, storage=form, max_nrhs=k) as h:
+        y = gpu_matvec(h, x, ld_pad=3)
+    assert_close(y, ref, FP32_TOL, ELEM_TOL)
+    if form == "fp16":
+        assert_close(y, oracle.oracle_matvec(data, x), 1e-3)
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16"])
+def test_multi_rhs_groups_alpha_beta_and_fewer_columns(form):
+    _log(f"case multi-rhs groups {form}")
+    data = make_hmatrix(uniform_tree(2, 64), 16, method="random", seed=8)
+    x = make_rhs(data.n, 130, 9)           # two groups: 128 + 2
+    y0 = np.random.default_rng(3).standard_normal((data.n, 130))
+    ref_data = dequantised(data, form)
+    ref = oracle.oracle_matvec(ref_data, x, alpha=0.5, beta=-1.25, y_in=y0.astype(np.float32))
+    with create(data, storage=form, max_nrhs=130) as h:
+        y = gpu_matvec(h, x, alpha=0.5, beta=-1.25, y0=y0)
+        assert_close(y, ref, FP32_TOL, ELEM_TOL)
+        # fewer columns than max_nrhs, and a single column, on the same handle
+        y7 = gpu_matvec(h, x[:, :7])
+        assert_close(y7, oracle.oracle_matvec(ref_data, x[:, :7]), FP32_TOL, ELEM_TOL)
+        y1 = gpu_matvec(h, x[:, :1])
+        assert_close(y1, oracle.oracle_matvec(ref_data, x[:, :1]), FP32_TOL, ELEM_TOL)
+        # deterministic
+        y7b = gpu_matvec(h, x[:, :7])
+        assert np.array_equal(y7, y7b)
+
+
+@pytest.fixture(scope="module")
+def c3_random():
+    _log("building c3-size factor set (3D, N=64^3, rank 64, random fill)")
+    data = make_hmatrix(uniform_tree(3, 64), 64, kind="inv", method="random", seed=23)
+    return data
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16"])
+def test_c3_full_size_multi_rhs(c3_random, form):
+    data = c3_random
+    _log(f"case c3 {form} full size, 64 RHS")
+    x = make_rhs(data.n, 64, 1003)
+    ref = oracle.oracle_matvec(dequantised(data, form), x)
+    with create(data, storage=form, max_nrhs=64) as h:
+        y = gpu_matvec(h, x)
+    assert_close(y, ref, FP32_TOL, ELEM_TOL)
