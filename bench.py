@@ -40,17 +40,19 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-c3", action="store_true", help="skip the multi-RHS (3D, 64 RHS) leg")
+    ap.add_argument("--c3-steps", type=int, default=20)
     return ap.parse_args()
 
 
-def time_matvecs(h, xd, yd, steps, warmup, stream):
+def time_matvecs(h, xd, yd, steps, warmup, stream, k=1):
     import torch
 
     import paper_2008_12441_amd as hm
 
     n = h.n
     for _ in range(warmup):
-        hm.hmat_matvec(h.handle, 1, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
+        hm.hmat_matvec(h.handle, k, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
     torch.cuda.synchronize()
     hm.hmat_set_timing(h.handle, True)
     start = torch.cuda.Event(enable_timing=True)
@@ -58,7 +60,7 @@ def time_matvecs(h, xd, yd, steps, warmup, stream):
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(steps):
-        hm.hmat_matvec(h.handle, 1, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
+        hm.hmat_matvec(h.handle, k, 1.0, xd.data_ptr(), n, 0.0, yd.data_ptr(), n, stream.cuda_stream)
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
@@ -113,6 +115,55 @@ def traffic_from_profile(kernel_key):
     if prof.get("kernel") != kernel_key or prof.get("kernel_source_sha256_16") != digest:
         return None
     return int(prof["traffic_bytes_per_launch"])
+
+
+def run_multi_rhs(stream, steps, warmup, with_oracle=True):
+    """3D 64^3 grid (N = 262144), 1/r kernel, rank 64, 64 RHS: FP32 vs FP16 storage on MFMA."""
+    import torch
+
+    import paper_2008_12441_amd as hm
+    from hmat_inputs import WORKLOADS, build_workload
+
+    w = WORKLOADS["c3"]
+    t0 = time.time()
+    data, x = build_workload("c3", device="cuda")
+    log(f"setup c3 ({w.describe()}): {time.time() - t0:.1f} s")
+    n, k = data.n, w.nrhs
+    t = data.tree
+    tree, blocks, keep = hm.make_descriptors(t.parent, t.begin, t.end, data.blocks.target, data.blocks.source,
+                                             data.blocks.rank, data.pool, data.off_a, data.off_b)
+    # x and y as k contiguous columns of length n (column-major n x k)
+    xd = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    flops = 2.0 * data.pool.size * k
+    vec_bytes = 2 * n * k * 4
+    out = {"workload": f"c3: {w.describe()}", "nrhs": k, "alg_flops_per_step": flops}
+    ys = {}
+    for form in ("fp32", "fp16"):
+        h = hm.HMatrix(tree, blocks, storage=form, max_nrhs=k)
+        yd = torch.empty_like(xd)
+        ms, ph = time_matvecs(h, xd, yd, steps, warmup, stream, k=k)
+        ys[form] = yd.cpu().numpy().T.astype(np.float64)
+        b = h.info["factor_bytes"] + vec_bytes
+        out[form] = {"ms_per_step": round(ms, 5), "GBps": round(b / (ms * 1e-3) / 1e9, 1),
+                     "TFLOPps": round(flops / (ms * 1e-3) / 1e12, 2), "alg_bytes_per_step": b,
+                     "phases_ms": [round(v, 5) for v in ph]}
+        log(f"c3 {form}: {ms:.4f} ms per {k}-RHS product, {out[form]['GBps']} GB/s, {out[form]['TFLOPps']} TFLOP/s")
+        h.close()
+    out["fp16_speedup_vs_fp32"] = round(out["fp32"]["ms_per_step"] / out["fp16"]["ms_per_step"], 3)
+    out["roofline"] = {"fp32": {"bound": "mfma", "peak": 157.3, "unit": "TFLOP/s",
+                                "frac": round(out["fp32"]["TFLOPps"] / 157.3, 4)},
+                       "fp16": {"bound": "hbm", "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                "frac": round(out["fp16"]["GBps"] / HBM_PEAK_GBPS, 4)}}
+    if with_oracle:
+        import oracle
+
+        t0 = time.time()
+        ref = oracle.oracle_matvec(data, x)
+        log(f"c3 oracle ({k} RHS): {time.time() - t0:.1f} s")
+        for form in ("fp32", "fp16"):
+            e = np.linalg.norm(ys[form] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            out[form]["rel_err_vs_fp64_oracle_max_col"] = float(e.max())
+    return out
 
 
 def main():
@@ -248,6 +299,16 @@ def main():
     }
     result.update(out_extra)
     h.close()
+    del h
+    if not args.no_c3:
+        import gc
+
+        import torch
+
+        del keep, tree, blocks, data
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["multi_rhs_c3"] = run_multi_rhs(stream, args.c3_steps, 3, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
 
 

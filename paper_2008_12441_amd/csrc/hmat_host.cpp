@@ -606,7 +606,7 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
 // ---------------------------------------------------------------------------
 // Multi-RHS (MFMA) layout.
 // ---------------------------------------------------------------------------
-constexpr int32_t kUnitChunks = 16;   // chunks a V-phase unit accumulates over
+constexpr int32_t kUnitChunks = 4;    // chunks a V-phase unit accumulates over
 constexpr int32_t kMaxRankMR = 128;
 
 struct HostPlanMR {
@@ -625,6 +625,7 @@ struct HostPlanMR {
     std::vector<int64_t> seg_block;            // low-rank block of a z segment, or -1
     std::vector<int32_t> seg_node;             // source leaf node of an x segment
     std::vector<hmat::MRTile> tiles;
+    std::vector<hmat::MRStep> ustep;
     std::vector<float> dscale;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> colmap;  // per node s: V column -> (block, j)
     std::vector<float> sU, sV, sD;
@@ -800,6 +801,22 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             hp.seg_node.push_back(hp.leaf_node[m.leaf_base + lf]);
         }
         m.nseg = (int32_t)hp.segs.size() - m.seg_base;
+        m.step_base = (int32_t)hp.ustep.size();
+        m.nsteps = seg_kb;
+        const int64_t bbytes = KB == 32 ? 2048 : 1024;
+        for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
+            const hmat::MRSeg &sg = hp.segs[si];
+            // B fragments: z fragments first, then X fragments, in one allocation;
+            // scale rows likewise: one per z item, then one per chunk
+            const int64_t base = sg.kind == 0 ? sg.src : hp.z_frags + sg.src;
+            for (int32_t kb = 0; kb < sg.nkb; ++kb) {
+                hmat::MRStep e;
+                e.bofs = (base + (int64_t)kb * hp.ntmax) * bbytes;
+                e.srow = sg.kind == 0 ? sg.sidx : (int32_t)hp.zitems.size() + sg.sidx;
+                e.sleaf = sg.kind == 0 ? -1 : sg.leaf;
+                hp.ustep.push_back(e);
+            }
+        }
         for (int32_t lf = 0; lf < m.nleaf; ++lf) {
             const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
             for (int32_t r0 = 0; r0 < e.rows; r0 += 64) {
@@ -989,16 +1006,15 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     const size_t bfrag = hp.kb == 32 ? 2048 : 1024;      // B fragment bytes
     void *q = nullptr;
     hmat_status s;
-    if ((s = dev_alloc(h, hp.x_frags * bfrag, &q)) != HMAT_OK) return s;
-    p.xpack = q;
-    if ((s = dev_alloc(h, hp.z_frags * bfrag, &q)) != HMAT_OK) return s;
+    if ((s = dev_alloc(h, (hp.z_frags + hp.x_frags) * bfrag, &q)) != HMAT_OK) return s;
     p.zpack = q;
+    p.xpack = static_cast<char *>(q) + hp.z_frags * bfrag;
     if ((s = dev_alloc(h, hp.part_floats * 4, &q)) != HMAT_OK) return s;
     p.part = static_cast<float *>(q);
-    if ((s = dev_alloc(h, hp.chunks.size() * hp.ntmax * 16 * 4, &q)) != HMAT_OK) return s;
-    p.sx = static_cast<float *>(q);
-    if ((s = dev_alloc(h, hp.zitems.size() * hp.ntmax * 16 * 4, &q)) != HMAT_OK) return s;
+    if ((s = dev_alloc(h, (hp.zitems.size() + hp.chunks.size()) * hp.ntmax * 4, &q)) != HMAT_OK) return s;
     p.sz = static_cast<float *>(q);
+    p.sx = p.sz + hp.zitems.size() * hp.ntmax;
+    p.scales = p.sz;
     if ((s = upload(h, hp.dscale, &p.dscale)) != HMAT_OK) return s;
     if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
     if ((s = upload(h, hp.leaves, &p.leaves)) != HMAT_OK) return s;
@@ -1006,6 +1022,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     if ((s = upload(h, hp.zitems, &p.zitems)) != HMAT_OK) return s;
     if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.ustep, &p.ustep)) != HMAT_OK) return s;
     void *vdev = nullptr, *uddev = nullptr;
     if ((s = dev_alloc(h, hp.v_frags * frag, &vdev)) != HMAT_OK) return s;
     if ((s = dev_alloc(h, hp.ud_frags * frag, &uddev)) != HMAT_OK) return s;
@@ -1033,7 +1050,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.num_tiles = (int32_t)hp.tiles.size();
     h->info.device_factor_bytes = (hp.v_frags + hp.ud_frags) * (int64_t)frag;
     h->info.workspace_bytes = (hp.x_frags + hp.z_frags) * (int64_t)bfrag + hp.part_floats * 4 +
-                              (int64_t)(hp.chunks.size() + hp.zitems.size()) * hp.ntmax * 64;
+                              (int64_t)(hp.chunks.size() + hp.zitems.size()) * hp.ntmax * 4;
     h->info.num_chunks = (int32_t)hp.chunks.size();
     return HMAT_OK;
 }

@@ -128,9 +128,9 @@ struct DevPlan {
 //    that box) the A fragments [chunk][K-block][m-subtile]; a wave computes
 //    the unit's V^T X and writes its partial sums (64 x 16 NT floats).
 //  * Xpack: per chunk the B fragments [K-block][n-tile] of X (FP16: hi/lo
-//    with one power-of-two scale per chunk and column).
+//    with one power-of-two scale per chunk and n-tile of 16 columns).
 //  * Zpack: per low-rank block the B fragments [K-block][n-tile] of its z
-//    (FP16: hi/lo, one power-of-two scale per block and column).
+//    (FP16: hi/lo, one power-of-two scale per block and n-tile).
 //  * UD panel: per row tile (<= 64 rows of one target leaf) the A fragments
 //    [K-block over its segments][m-subtile]; segments are the z of every
 //    ancestor-level block, then x over each source leaf.
@@ -144,7 +144,9 @@ struct MRChunk {
     int32_t seg_base;     // first U-phase segment
     int32_t nseg;
     int32_t dscale_base;  // nleaf x nleaf dense-block scales
-    int64_t xoff;         // first B fragment of its Xpack
+    int64_t xoff;         // first B fragment of its Xpack (relative to xpack)
+    int32_t step_base;    // first entry of its U-phase step table
+    int32_t nsteps;       // K-block steps over all its segments
 };
 
 struct MRLeaf {
@@ -191,6 +193,12 @@ struct MRTile {
     int32_t pad_;
 };
 
+struct MRStep {           // one K-block step of a chunk's target-side contraction
+    int64_t bofs;         // byte offset of its B fragments from zpack (xpack follows zpack)
+    int32_t srow;         // row of its n-tile scales in the scale array (z rows, then x rows)
+    int32_t sleaf;        // source leaf (x steps: selects the dense-block scale), -1 for z steps
+};
+
 struct DevPlanMR {
     int32_t storage;
     int32_t ntmax;            // n-tiles of 16 columns allocated (max_nrhs / 16, rounded up)
@@ -200,11 +208,11 @@ struct DevPlanMR {
     int32_t num_tiles;
     const void *V;            // A fragments
     const void *UD;
-    void *xpack;              // B fragments
-    void *zpack;
+    void *xpack;              // B fragments of X (in the same allocation as zpack, after it)
+    void *zpack;              // B fragments of z
     float *part;              // unit partial sums
-    float *sx;                // per chunk x 16 NT column scales of Xpack
-    float *sz;                // per block x 16 NT column scales of Zpack
+    float *sx;                // per chunk x ntmax n-tile scales of Xpack
+    float *sz;                // per block x ntmax n-tile scales of Zpack
     const float *dscale;
     const MRChunk *chunks;
     const MRLeaf *leaves;
@@ -212,6 +220,8 @@ struct DevPlanMR {
     const MRZItem *zitems;
     const MRSeg *segs;
     const MRTile *tiles;
+    const MRStep *ustep;      // per chunk step (MRChunk::step_base)
+    const float *scales;      // n-tile scales: sz rows (one per z item), then sx rows (one per chunk)
 };
 
 // Kernel launchers (hmat_kernels.hip). Each returns a hipError_t as int.

@@ -28,8 +28,33 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxRankMR = 128;
 
+// waves per SIMD the MFMA kernels are compiled for: two while the
+// accumulators and the double-buffered fragments fit in 256 registers
+template <int NT>
+struct Occupancy {
+    static constexpr int waves = NT <= 4 ? 2 : 1;
+};
+
 template <int STORE>
 struct MR;
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+// A buffer resource starting at p (raw, byte offsets below 4 GiB).
+__device__ inline rsrc_t make_rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, -1, 0x00020000);
+}
+
+constexpr int kNontemporal = 2;  // cache-policy bits of a streaming (read-once) load
+
+// Uniform (wave-wide) values read through the scalar cache.
+typedef __attribute__((address_space(4))) const float cfloat;
+__device__ inline float sload(const float *p, int i) { return ((cfloat *)p)[i]; }
+
+template <int AUX>
+__device__ inline f32x4 buf16(rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+}
 
 template <>
 struct MR<HMAT_STORE_FP32> {
@@ -41,12 +66,11 @@ struct MR<HMAT_STORE_FP32> {
     struct B {
         f32x4 v;
     };
-    __device__ static inline A loadA(const void *base, int64_t frag, int lane) {
-        return __builtin_nontemporal_load(static_cast<const f32x4 *>(base) + frag * 64 + lane);
-    }
-    __device__ static inline B loadB(const void *base, int64_t frag, int lane) {
+    // A fragment at byte offset soff of r; lane l reads bytes [16 l, 16 l + 16)
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) { return buf16<kNontemporal>(r, lane * 16, soff); }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
         B b;
-        b.v = static_cast<const f32x4 *>(base)[frag * BFRAG + lane];
+        b.v = buf16<0>(r, lane * 16, soff);
         return b;
     }
     __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
@@ -71,14 +95,13 @@ struct MR<HMAT_STORE_FP16_SCALED> {
     struct B {
         f16x8 hi, lo;
     };
-    __device__ static inline A loadA(const void *base, int64_t frag, int lane) {
-        return __builtin_nontemporal_load(static_cast<const f16x8 *>(base) + frag * 64 + lane);
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) {
+        return __builtin_bit_cast(f16x8, buf16<kNontemporal>(r, lane * 16, soff));
     }
-    __device__ static inline B loadB(const void *base, int64_t frag, int lane) {
-        const f16x8 *p = static_cast<const f16x8 *>(base) + frag * BFRAG + lane;
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
         B b;
-        b.hi = p[0];
-        b.lo = p[64];
+        b.hi = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16, soff));
+        b.lo = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16 + 1024, soff));
         return b;
     }
     // v is already divided by the column scale: split into two halves whose
@@ -119,49 +142,161 @@ __device__ inline int wave_id(int waves_per_block) {
     return __builtin_amdgcn_readfirstlane((int)blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6));
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (block i runs on XCD i % 8), and
+// each XCD has its own L2. Renumbering the blocks so that every XCD works
+// through one contiguous range of tiles keeps the B fragments that
+// neighbouring tiles share (a chunk's X, its ancestors' z) in one L2.
+constexpr int kXcds = 8;
+__device__ inline int wave_id_xcd(int waves_per_block) {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b % kXcds, j = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int logical = x * per + (x < rem ? x : rem) + j;
+    return __builtin_amdgcn_readfirstlane(logical * waves_per_block + (int)(threadIdx.x >> 6));
+}
+
+// ---------------------------------------------------------------------------
+// The K-block step loop shared by both contractions. Step s multiplies the A
+// fragments af0 + s * nm + m (m < nm) with the B fragments that info(s)
+// points at (n-tile t at + t * 16 * BFRAG bytes). In the scaled form the B
+// values of step s carry the n-tile scales info(s).srow[t] * info(s).fac;
+// whenever those change, the accumulators are moved to the new scales
+// (powers of two, so the move is exact). info is called in increasing s.
+// ---------------------------------------------------------------------------
+struct StepInfo {
+    int64_t bofs;        // byte offset of the step's B fragments
+    const float *srow;   // n-tile scales of the step's B (scaled form)
+    float fac;           // extra power-of-two factor of those scales
+};
+
+template <int STORE, int NT, class Info>
+__device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int nm, int nsteps, int lane, Info info,
+                                  f32x4 (&acc)[4][NT], float (&scur)[NT]) {
+    using F = MR<STORE>;
+    if (nsteps <= 0) return;
+    const rsrc_t ra = make_rsrc(static_cast<const char *>(A) + af0 * 1024);
+    // Four register sets for A (loaded four steps ahead), two for B (one step
+    // ahead). Every load is issued unconditionally, with indices clamped to
+    // the last step and m-subtile (re-reading fragments already in cache):
+    // loads under branches make the wait counters conservative and would
+    // drain the prefetched fragments at every step.
+    typename F::A a0[4], a1[4], a2[4], a3[4];
+    typename F::B b0[NT], b1[NT];
+    auto load_a = [&](typename F::A(&a)[4], int st) {
+        const int sc = st < nsteps ? st : nsteps - 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
+    };
+    auto load_b = [&](typename F::B(&b)[NT], int64_t bofs) {
+        const rsrc_t rb = make_rsrc(static_cast<const char *>(B) + bofs);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = F::loadB(rb, t * 16 * F::BFRAG, lane);
+    };
+    // scales of the current step's B and whether they differ from the last
+    // step's; the next step's are read one step ahead (scalar loads)
+    StepInfo ic = info(0), in_;
+    float sc[NT], sn[NT];
+    bool chg_c = true, chg_n = false;
+    if (F::SCALED) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sc[t] = sload(ic.srow, t) * ic.fac;
+    }
+    auto step = [&](typename F::A(&a)[4], typename F::B(&b)[NT], typename F::B(&bn)[NT], int st) {
+        in_ = info(st + 1 < nsteps ? st + 1 : nsteps - 1);
+        load_b(bn, in_.bofs);
+        if (F::SCALED) {
+            chg_n = in_.srow != ic.srow || in_.fac != ic.fac;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sn[t] = chg_n ? sload(in_.srow, t) * in_.fac : sc[t];
+            if (chg_c) {  // this step's B carries new n-tile scales: move the accumulators
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const float f = scur[t] * __builtin_amdgcn_rcpf(sc[t]);  // powers of two: exact
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) acc[m][t] *= f;
+                    scur[t] = sc[t];
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (m < nm)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) F::mma(a[m], b[t], acc[m][t]);
+        load_a(a, st + 4);
+        ic = in_;
+        if (F::SCALED) {
+            chg_c = chg_n;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sc[t] = sn[t];
+        }
+    };
+    load_b(b0, ic.bofs);
+    load_a(a0, 0);
+    load_a(a1, 1);
+    load_a(a2, 2);
+    load_a(a3, 3);
+    for (int st = 0; st < nsteps; st += 4) {
+        step(a0, b0, b1, st);
+        if (st + 1 >= nsteps) break;
+        step(a1, b1, b0, st + 1);
+        if (st + 2 >= nsteps) break;
+        step(a2, b0, b1, st + 2);
+        if (st + 3 >= nsteps) break;
+        step(a3, b1, b0, st + 3);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // X -> B fragments, one workgroup per chunk.
 // ---------------------------------------------------------------------------
 template <int STORE>
 __global__ __launch_bounds__(256) void k_xpack(DevPlanMR p, const float *__restrict__ x, int64_t ldx, int k) {
+    // one workgroup per (chunk, n-tile of 16 columns)
     using F = MR<STORE>;
     constexpr int VW = F::VW;
     constexpr int KB = F::KB;
-    __shared__ float sig[128];
-    const int c = blockIdx.x;
-    const MRChunk ch = p.chunks[c];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ float red[16][17];
+    __shared__ float sig[1];
     const int nt_used = (k + 15) / 16;
-    const int ncol = p.ntmax * 16;
+    const int c = blockIdx.x / nt_used, nt = blockIdx.x % nt_used;
+    const MRChunk ch = p.chunks[c];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (F::SCALED) {
-        for (int n = wave; n < nt_used * 16; n += 4) {
-            float m = 0.0f;
-            if (n < k)
-                for (int i = lane; i < ch.rows; i += 64) m = fmaxf(m, fabsf(x[(int64_t)(ch.row_begin + i) + n * ldx]));
-            m = wave_max(m);
-            const float s = col_scale(m);
-            if (lane == 0) {
-                sig[n] = s;
-                p.sx[(int64_t)c * ncol + n] = s;
-            }
+        // 16 threads per column read 16 consecutive rows at a time
+        const int cc = tid >> 4, r0 = tid & 15;
+        const int n = nt * 16 + cc;
+        float m = 0.0f;
+        if (n < k) {
+            const float *col = x + (int64_t)n * ldx + ch.row_begin;
+            for (int i = r0; i < ch.rows; i += 16) m = fmaxf(m, fabsf(col[i]));
+        }
+        red[cc][r0] = m;
+        __syncthreads();
+        if (tid == 0) {
+            float a = 0.0f;
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j) a = fmaxf(a, red[i][j]);
+            const float s = col_scale(a);
+            sig[0] = s;
+            p.sx[(int64_t)c * p.ntmax + nt] = s;
         }
         __syncthreads();
     }
-    const int nfrag = ch.nkb * nt_used;
-    for (int f = wave; f < nfrag; f += 4) {
-        const int kb = f / nt_used, nt = f % nt_used;
-        const int n = nt * 16 + (lane & 15);
+    const int n = nt * 16 + (lane & 15);
+    const float inv = F::SCALED ? 1.0f / sig[0] : 1.0f;
+    const float *col = x + (int64_t)n * ldx;
+    for (int kb = wave; kb < ch.nkb; kb += 4) {
         // the leaf holding this K-block (leaves start on K-block boundaries)
         int lf = 0;
         while (lf + 1 < ch.nleaf && p.leaves[ch.leaf_base + lf + 1].kb0 <= kb) ++lf;
         const MRLeaf L = p.leaves[ch.leaf_base + lf];
         const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
-        const float inv = F::SCALED ? 1.0f / sig[nt * 16 + (lane & 15)] : 1.0f;
         float v[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int o = off0 + e;
-            v[e] = (n < k && o < L.rows) ? x[(int64_t)(L.row_begin + o) + n * ldx] * inv : 0.0f;
+            v[e] = (n < k && o < L.rows) ? col[L.row_begin + o] * inv : 0.0f;
         }
         F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, v);
     }
@@ -171,13 +306,12 @@ __global__ __launch_bounds__(256) void k_xpack(DevPlanMR p, const float *__restr
 // Source side: one wave per unit; acc[m-subtile][n-tile] are 16x16 tiles.
 // ---------------------------------------------------------------------------
 template <int STORE, int NT>
-__global__ __launch_bounds__(256) void k_vmfma(DevPlanMR p) {
+__global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_vmfma(DevPlanMR p) {
     using F = MR<STORE>;
     const int w = wave_id(4);
     if (w >= p.num_vunits) return;
     const int lane = threadIdx.x & 63;
     const MRVUnit u = p.vunits[w];
-    const int nm = u.nm;
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -187,35 +321,22 @@ __global__ __launch_bounds__(256) void k_vmfma(DevPlanMR p) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) scur[t] = 1.0f;
     const int ncol = p.ntmax * 16;
-    int64_t af = u.aoff;
-    for (int c = u.c0; c < u.c0 + u.nc; ++c) {
-        const MRChunk ch = p.chunks[c];
-        if (F::SCALED) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float s = p.sx[(int64_t)c * ncol + t * 16 + (lane & 15)];
-                const float f = scur[t] / s;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) acc[m][t] *= f;
-                scur[t] = s;
-            }
+    // The unit's A fragments are [step][m-subtile] and its chunks' X
+    // fragments [step][n-tile], both contiguous over the unit's steps.
+    constexpr int64_t bbytes = 16 * F::BFRAG;
+    const int64_t b0 = p.chunks[u.c0].xoff;
+    int nsteps = 0;
+    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += p.chunks[c].nkb;
+    int c = u.c0 - 1, cend = 0;  // chunk of the step asked for last, and the step where it ends
+    const int64_t ntm = p.ntmax;
+    auto info = [&](int st) {
+        while (st >= cend) {
+            ++c;
+            cend += p.chunks[c].nkb;
         }
-        for (int kb = 0; kb < ch.nkb; ++kb) {
-            typename F::A a[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nm) a[m] = F::loadA(p.V, af + (int64_t)kb * nm + m, lane);
-            typename F::B b[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = F::loadB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + t, lane);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nm)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) F::mma(a[m], b[t], acc[m][t]);
-        }
-        af += (int64_t)ch.nkb * nm;
-    }
+        return StepInfo{(b0 + (int64_t)st * ntm) * bbytes, p.sx + (int64_t)c * ntm, 1.0f};
+    };
+    mfma_steps<STORE, NT>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, acc, scur);
     float *out = p.part + u.poff;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -260,10 +381,9 @@ __global__ __launch_bounds__(256) void k_zmfma(DevPlanMR p, int nt_used) {
         zs[wave][j][nn] = s;
         amax = fmaxf(amax, fabsf(s));
     }
-    amax = fmaxf(amax, __shfl_xor(amax, 16));
-    amax = fmaxf(amax, __shfl_xor(amax, 32));
+    amax = wave_max(amax);
     const float sig = F::SCALED ? col_scale(amax) : 1.0f;
-    if (F::SCALED && g == 0) p.sz[(int64_t)item * ncol + n] = sig;
+    if (F::SCALED && lane == 0) p.sz[(int64_t)item * p.ntmax + nt] = sig;
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     const float inv = 1.0f / sig;
@@ -283,16 +403,15 @@ __global__ __launch_bounds__(256) void k_zmfma(DevPlanMR p, int nt_used) {
 // Target side: one wave per row tile (<= 64 rows of one target leaf).
 // ---------------------------------------------------------------------------
 template <int STORE, int NT>
-__global__ __launch_bounds__(256) void k_umfma(DevPlanMR p, int k, float alpha, float beta, float *__restrict__ y,
-                                               int64_t ldy) {
+__global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_umfma(DevPlanMR p, int k, float alpha, float beta,
+                                                                     float *__restrict__ y, int64_t ldy) {
     using F = MR<STORE>;
-    const int w = wave_id(4);
+    const int w = wave_id_xcd(4);
     if (w >= p.num_tiles) return;
     const int lane = threadIdx.x & 63;
     const MRTile tl = p.tiles[w];
     const MRChunk ch = p.chunks[tl.chunk];
     const int nm = tl.nm;
-    const int ncol = p.ntmax * 16;
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -301,38 +420,15 @@ __global__ __launch_bounds__(256) void k_umfma(DevPlanMR p, int k, float alpha, 
     float scur[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) scur[t] = 1.0f;
-    int64_t af = tl.aoff;
-    for (int si = ch.seg_base; si < ch.seg_base + ch.nseg; ++si) {
-        const MRSeg sg = p.segs[si];
-        if (F::SCALED) {
-            const float ds = sg.kind ? p.dscale[ch.dscale_base + tl.tleaf * ch.nleaf + sg.leaf] : 1.0f;
-            const float *srow = (sg.kind ? p.sx : p.sz) + (int64_t)sg.sidx * ncol;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float s = srow[t * 16 + (lane & 15)] * ds;
-                const float f = scur[t] / s;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) acc[m][t] *= f;
-                scur[t] = s;
-            }
-        }
-        const void *bsrc = sg.kind ? p.xpack : p.zpack;
-        for (int kb = 0; kb < sg.nkb; ++kb) {
-            typename F::A a[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nm) a[m] = F::loadA(p.UD, af + (int64_t)kb * nm + m, lane);
-            typename F::B b[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = F::loadB(bsrc, sg.src + (int64_t)kb * p.ntmax + t, lane);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nm)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) F::mma(a[m], b[t], acc[m][t]);
-        }
-        af += (int64_t)sg.nkb * nm;
-    }
+    // A fragments are contiguous over the tile's steps; the chunk's step
+    // table gives each step's B fragment (z of a block, or x of a source leaf).
+    const MRStep *steps = p.ustep + ch.step_base;
+    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nleaf;  // this target leaf's dense scales
+    auto info = [&](int st) {
+        const MRStep e = steps[st];
+        return StepInfo{e.bofs, p.scales + (int64_t)e.srow * p.ntmax, e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f};
+    };
+    mfma_steps<STORE, NT>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, acc, scur);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -355,7 +451,7 @@ template <int STORE, int NT>
 int launch_mr_nt(const DevPlanMR &p, int32_t k, float alpha, const float *x, int64_t ldx, float beta, float *y,
                  int64_t ldy, hipStream_t st, void (*mark)(void *, int), void *ctx) {
     if (mark) mark(ctx, 0);
-    hipLaunchKernelGGL(k_xpack<STORE>, dim3(p.num_chunks), dim3(256), 0, st, p, x, ldx, k);
+    hipLaunchKernelGGL(k_xpack<STORE>, dim3(p.num_chunks * NT), dim3(256), 0, st, p, x, ldx, k);
     int e = (int)hipGetLastError();
     if (e) return e;
     if (p.num_vunits > 0) {
