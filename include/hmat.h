@@ -43,8 +43,9 @@ typedef enum hmat_status {
  * FP32 in every form. */
 typedef enum hmat_storage {
     HMAT_STORE_FP32 = 0,          /* D, U, V in FP32 */
-    HMAT_STORE_FP16_SCALED = 1    /* D, U, V in FP16, one power-of-two scale per stored array
+    HMAT_STORE_FP16_SCALED = 1,   /* D, U, V in FP16, one power-of-two scale per stored array
                                      D_ts, U_ts, V_ts: s = 2^(ceil(log2 amax) - 15), q = RNE(v / s) */
+    HMAT_STORE_BF16 = 2           /* D, U, V in BF16, q = RNE(v), no scales */
 } hmat_storage;
 
 /* Domain tree (Def. "Domain tree", Sec. 2). Node 0 is the root with

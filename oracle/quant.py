@@ -1,9 +1,10 @@
 """Dequantised factor sets for the low-precision storage forms -- TEST INFRASTRUCTURE ONLY.
 
-Written independently of the GPU library's quantiser, from the storage rule:
-FP16 with one power-of-two scale per stored array (each D_ts, U_ts, V_ts):
-s = 2^(ceil(log2 amax) - 15), q = round-to-nearest-even(v / s) to IEEE half
-(numpy's float16 cast), dequantised value q * s (exact in FP32).
+Written independently of the GPU library's quantiser, from the storage rules:
+  fp16  one power-of-two scale per stored array (each D_ts, U_ts, V_ts):
+        s = 2^(ceil(log2 amax) - 15), q = round-to-nearest-even(v / s) to IEEE
+        half (numpy's float16 cast), dequantised value q * s (exact in FP32);
+  bf16  q = round-to-nearest-even(v) to bfloat16 (torch's CPU cast).
 """
 from __future__ import annotations
 
@@ -31,10 +32,21 @@ def _dequant_fp16(a: np.ndarray) -> np.ndarray:
     return (q.astype(np.float64) * s).astype(np.float32)
 
 
+def _dequant_bf16(pool: np.ndarray) -> np.ndarray:
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(pool, dtype=np.float32))
+    return t.to(torch.bfloat16).to(torch.float32).numpy()
+
+
 def dequantised(data, form: str):
     """A copy of ``data`` (HMatrixData) whose pool holds the dequantised factors."""
     if form == "fp32":
         return data
+    if form == "bf16":
+        out = copy.copy(data)
+        out.pool = _dequant_bf16(data.pool)
+        return out
     if form != "fp16":
         raise ValueError(form)
     out = copy.copy(data)

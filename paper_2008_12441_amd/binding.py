@@ -24,7 +24,8 @@ HMAT_ERR_DEVICE = 6
 
 HMAT_STORE_FP32 = 0
 HMAT_STORE_FP16_SCALED = 1
-STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED}
+HMAT_STORE_BF16 = 2
+STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED, "bf16": HMAT_STORE_BF16}
 
 HMAT_NUM_PHASES = 3
 

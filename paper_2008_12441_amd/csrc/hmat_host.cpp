@@ -106,6 +106,22 @@ uint16_t f32_to_f16_rne(float v) {
     return (uint16_t)(sign | h);
 }
 
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+uint16_t f32_to_bf16_rne(float v) {
+    uint32_t x;
+    std::memcpy(&x, &v, 4);
+    if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
+    const uint32_t lsb = (x >> 16) & 1u;
+    x += 0x7fffu + lsb;
+    return (uint16_t)(x >> 16);
+}
+
+// 16-bit code of v in the storage form: FP16 of v * inv (inv = 1 / scale, a
+// power of two, so the product is exact) or BF16 of v.
+inline uint16_t quant16(float v, float inv, bool bf16) {
+    return bf16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v * inv);
+}
+
 float pow2_scale_f16(float amax) {
     if (!(amax > 0.0f)) return 1.0f;
     int e = 0;
@@ -285,6 +301,7 @@ hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb
 // ---------------------------------------------------------------------------
 struct HostPlan {
     int32_t vw = 4;                 // elements per 16-byte vector
+    bool bf16 = false;              // 16-bit codes are BF16 (else scaled FP16)
     int32_t chunk_depth = 0;
     std::vector<int32_t> chunk_node;
     std::vector<ChunkMeta> chunks;
@@ -308,7 +325,8 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
                        int32_t storage, HostPlan &hp) {
-    hp.vw = storage == HMAT_STORE_FP16_SCALED ? 8 : 4;
+    hp.vw = storage == HMAT_STORE_FP32 ? 4 : 8;
+    hp.bf16 = storage == HMAT_STORE_BF16;
     const int32_t vw = hp.vw;
     const int32_t L = t.L;
     const int32_t cd = std::max(L - 1, 0);
@@ -336,17 +354,23 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
     hp.sU.assign(nb, 1.0f);
     hp.sV.assign(nb, 1.0f);
     hp.sD.assign(nb, 1.0f);
-    if (storage == HMAT_STORE_FP16_SCALED) {
+    if (storage != HMAT_STORE_FP32) {
+        const bool scaled = storage == HMAT_STORE_FP16_SCALED;
         std::atomic<bool> ok{true};
         parallel_for(nb, [&](int64_t b) {
             bool fin = true;
             const hmat_block_desc &d = bl[b];
             const int64_t mt = t.size(d.target), ms = t.size(d.source);
             if (d.rank == 0) {
-                hp.sD[b] = pow2_scale_f16(col_major_amax(d.a, mt, ms, d.lda, &fin));
+                const float a = col_major_amax(d.a, mt, ms, d.lda, &fin);
+                if (scaled) hp.sD[b] = pow2_scale_f16(a);
             } else {
-                hp.sU[b] = pow2_scale_f16(col_major_amax(d.a, mt, d.rank, d.lda, &fin));
-                hp.sV[b] = pow2_scale_f16(col_major_amax(d.b, ms, d.rank, d.ldb, &fin));
+                const float au = col_major_amax(d.a, mt, d.rank, d.lda, &fin);
+                const float av = col_major_amax(d.b, ms, d.rank, d.ldb, &fin);
+                if (scaled) {
+                    hp.sU[b] = pow2_scale_f16(au);
+                    hp.sV[b] = pow2_scale_f16(av);
+                }
             }
             if (!fin) ok = false;
         });
@@ -525,7 +549,7 @@ void fill_v(const Tree &t, const Structure &st, const hmat_block_desc *bl, const
                         const float v = i < m.rows ? src[i] : 0.0f;
                         T q;
                         if constexpr (sizeof(T) == 4) q = v;
-                        else q = f32_to_f16_rne(v * inv);
+                        else q = quant16(v, inv, hp.bf16);
                         dst[((int64_t)(i / vw) * hmat::kWave + l) * vw + i % vw] = q;
                     }
                 }
@@ -565,7 +589,7 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
                     for (int32_t i = 0; i < prow; ++i) {
                         const float v = i < m.rows ? src[i] : 0.0f;
                         if constexpr (sizeof(T) == 4) put(i, col, v);
-                        else put(i, col, f32_to_f16_rne(v * inv));
+                        else put(i, col, quant16(v, inv, hp.bf16));
                     }
                 }
             }
@@ -595,7 +619,7 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
                         inv = 1.0f / hp.sD[b];
                     }
                     if constexpr (sizeof(T) == 4) put(i, qcol, v);
-                    else put(i, qcol, f32_to_f16_rne(v * inv));
+                    else put(i, qcol, quant16(v, inv, hp.bf16));
                 }
             }
         }
@@ -611,6 +635,7 @@ constexpr int32_t kMaxRankMR = 128;
 
 struct HostPlanMR {
     int32_t kb = 16, vw = 4, ntmax = 1;
+    bool bf16 = false;
     int32_t chunk_depth = 0;
     std::vector<int32_t> chunk_node;
     std::vector<int32_t> anc;                  // chunk x (chunk_depth + 1)
@@ -635,8 +660,10 @@ struct HostPlanMR {
 hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
                           int32_t storage, int32_t max_nrhs, HostPlanMR &hp) {
     const bool f16 = storage == HMAT_STORE_FP16_SCALED;
-    hp.kb = f16 ? 32 : 16;
-    hp.vw = f16 ? 8 : 4;
+    const bool half = storage != HMAT_STORE_FP32;  // 16-bit codes (FP16 or BF16)
+    hp.bf16 = storage == HMAT_STORE_BF16;
+    hp.kb = half ? 32 : 16;
+    hp.vw = half ? 8 : 4;
     hp.ntmax = (std::min(max_nrhs, 128) + 15) / 16;
     const int32_t KB = hp.kb, L = t.L, cd = std::max(L - 1, 0);
     hp.chunk_depth = cd;
@@ -662,17 +689,22 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
     hp.sU.assign(nb, 1.0f);
     hp.sV.assign(nb, 1.0f);
     hp.sD.assign(nb, 1.0f);
-    if (f16) {
+    if (half) {
         std::atomic<bool> ok{true};
         parallel_for(nb, [&](int64_t b) {
             bool fin = true;
             const hmat_block_desc &d = bl[b];
             const int64_t mt = t.size(d.target), ms = t.size(d.source);
             if (d.rank == 0) {
-                hp.sD[b] = pow2_scale_f16(col_major_amax(d.a, mt, ms, d.lda, &fin));
+                const float a = col_major_amax(d.a, mt, ms, d.lda, &fin);
+                if (f16) hp.sD[b] = pow2_scale_f16(a);
             } else {
-                hp.sU[b] = pow2_scale_f16(col_major_amax(d.a, mt, d.rank, d.lda, &fin));
-                hp.sV[b] = pow2_scale_f16(col_major_amax(d.b, ms, d.rank, d.ldb, &fin));
+                const float au = col_major_amax(d.a, mt, d.rank, d.lda, &fin);
+                const float av = col_major_amax(d.b, ms, d.rank, d.ldb, &fin);
+                if (f16) {
+                    hp.sU[b] = pow2_scale_f16(au);
+                    hp.sV[b] = pow2_scale_f16(av);
+                }
             }
             if (!fin) ok = false;
         });
@@ -847,12 +879,13 @@ inline int32_t mr_row(const HostPlanMR &hp, const hmat::MRChunk &m, int32_t pr) 
 }
 
 template <class T>
-inline T quant(float v, float scale) {
+inline T quant(float v, float scale, bool bf16) {
     if constexpr (sizeof(T) == 4) {
         (void)scale;
+        (void)bf16;
         return v;
     } else {
-        return f32_to_f16_rne(v / scale);
+        return quant16(v, 1.0f / scale, bf16);
     }
 }
 
@@ -881,7 +914,7 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
                                 v = d.b[(gr - t.begin[s]) + (int64_t)cm[col].second * d.ldb];
                                 sc = hp.sV[b];
                             }
-                            fr[l * vw + e] = quant<T>(v, sc);
+                            fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
                         }
                     }
                 }
@@ -917,7 +950,7 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
                             float v = 0.0f;
                             if (tr < tl.rows && kk < ncols)
                                 v = d.a[(tl.row0 + tr - rbase) + (int64_t)kk * d.lda];
-                            fr[l * vw + e] = quant<T>(v, sc);
+                            fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
                         }
                     }
                 }
@@ -1058,7 +1091,8 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
 hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t nb,
                         const hmat_options *opts, hmat_handle *h) {
     if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
-    if (opts->storage != HMAT_STORE_FP32 && opts->storage != HMAT_STORE_FP16_SCALED)
+    if (opts->storage != HMAT_STORE_FP32 && opts->storage != HMAT_STORE_FP16_SCALED &&
+        opts->storage != HMAT_STORE_BF16)
         return fail(HMAT_ERR_INVALID_ARG, "unknown storage form");
     if (opts->max_nrhs < 1) return fail(HMAT_ERR_INVALID_ARG, "max_nrhs must be >= 1");
     if (opts->device < 0) return fail(HMAT_ERR_INVALID_ARG, "device must be >= 0");
@@ -1097,7 +1131,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     in.num_dense_blocks = nd;
     in.num_lowrank_blocks = nl;
     in.stored_elements = elems;
-    const int64_t esz = opts->storage == HMAT_STORE_FP16_SCALED ? 2 : 4;
+    const int64_t esz = opts->storage == HMAT_STORE_FP32 ? 4 : 2;
     in.factor_bytes = elems * esz + (opts->storage == HMAT_STORE_FP16_SCALED ? 4 * (nd + 2 * nl) : 0);
     in.device_factor_bytes = (hp.v_elems + hp.ud_elems) * esz;
     in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * 4;
@@ -1105,7 +1139,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     in.max_nrhs = opts->max_nrhs;
 
     if (h->mr) {
-        if (opts->storage == HMAT_STORE_FP16_SCALED) return upload_mr<uint16_t>(h, t, st, blocks, hpm);
+        if (opts->storage != HMAT_STORE_FP32) return upload_mr<uint16_t>(h, t, st, blocks, hpm);
         return upload_mr<float>(h, t, st, blocks, hpm);
     }
 
@@ -1137,7 +1171,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     if ((s = upload(h, hp.vtiles, &p.vtiles)) != HMAT_OK) return s;
     if ((s = upload(h, hp.z1, &p.z1)) != HMAT_OK) return s;
     if ((s = upload(h, hp.z2, &p.z2)) != HMAT_OK) return s;
-    if (opts->storage == HMAT_STORE_FP16_SCALED)
+    if (opts->storage != HMAT_STORE_FP32)
         s = upload_panels<uint16_t>(h, t, st, blocks, hp);
     else
         s = upload_panels<float>(h, t, st, blocks, hp);

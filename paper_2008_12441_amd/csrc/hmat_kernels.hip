@@ -50,6 +50,22 @@ struct Form<HMAT_STORE_FP16_SCALED> {
     }
 };
 
+template <>
+struct Form<HMAT_STORE_BF16> {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    using Vec = u32x4;
+    using Elem = unsigned short;
+    static constexpr int VW = 8;
+    __device__ static inline void load(const Vec *p, float (&v)[VW]) {
+        const Vec t = __builtin_nontemporal_load(p);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {  // a BF16 code is the top half of an FP32 word
+            v[2 * e] = __builtin_bit_cast(float, t[e] << 16);
+            v[2 * e + 1] = __builtin_bit_cast(float, t[e] & 0xffff0000u);
+        }
+    }
+};
+
 #ifndef HMAT_VUNROLL
 #define HMAT_VUNROLL 8
 #endif
@@ -285,6 +301,8 @@ int launch_vphase(const DevPlan &p, const float *x, void *stream) {
     const int blocks = (p.num_vtiles + 3) / 4;
     if (p.storage == HMAT_STORE_FP16_SCALED)
         hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP16_SCALED>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+    else if (p.storage == HMAT_STORE_BF16)
+        hipLaunchKernelGGL(k_vphase<HMAT_STORE_BF16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
     else
         hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
     return (int)hipGetLastError();
@@ -303,6 +321,9 @@ int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float
     if (p.storage == HMAT_STORE_FP16_SCALED)
         hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP16_SCALED>, dim3(p.num_chunks), dim3(256), lds,
                            (hipStream_t)stream, p, x, y, alpha, beta);
+    else if (p.storage == HMAT_STORE_BF16)
+        hipLaunchKernelGGL(k_uphase<HMAT_STORE_BF16>, dim3(p.num_chunks), dim3(256), lds, (hipStream_t)stream,
+                           p, x, y, alpha, beta);
     else
         hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP32>, dim3(p.num_chunks), dim3(256), lds, (hipStream_t)stream, p,
                            x, y, alpha, beta);

@@ -123,6 +123,45 @@ struct MR<HMAT_STORE_FP16_SCALED> {
     }
 };
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <>
+struct MR<HMAT_STORE_BF16> {
+    static constexpr int KB = 32;
+    static constexpr int VW = 8;
+    static constexpr int BFRAG = 128;   // hi (64 slots) then lo (64 slots)
+    static constexpr bool SCALED = false;  // BF16 keeps FP32's exponent range
+    using A = bf16x8;
+    struct B {
+        bf16x8 hi, lo;
+    };
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) {
+        return __builtin_bit_cast(bf16x8, buf16<kNontemporal>(r, lane * 16, soff));
+    }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
+        B b;
+        b.hi = __builtin_bit_cast(bf16x8, buf16<0>(r, lane * 16, soff));
+        b.lo = __builtin_bit_cast(bf16x8, buf16<0>(r, lane * 16 + 1024, soff));
+        return b;
+    }
+    // two BF16 parts whose sum carries about 16 significant bits
+    __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            hi[e] = (__bf16)v[e];
+            lo[e] = (__bf16)(v[e] - (float)hi[e]);
+        }
+        bf16x8 *p = static_cast<bf16x8 *>(base) + frag * BFRAG + lane;
+        p[0] = hi;
+        p[64] = lo;
+    }
+    __device__ static inline void mma(const A &a, const B &b, f32x4 &c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, c, 0, 0, 0);
+    }
+};
+
 // power of two with |v| / s <= 2^14 for |v| <= amax (1 for amax == 0)
 __device__ inline float col_scale(float amax) {
     if (!(amax > 0.0f)) return 1.0f;
@@ -495,6 +534,8 @@ int launch_mr(const DevPlanMR &p, int32_t k, float alpha, const float *x, int64_
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.storage == HMAT_STORE_FP16_SCALED)
         return launch_mr_form<HMAT_STORE_FP16_SCALED>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
+    if (p.storage == HMAT_STORE_BF16)
+        return launch_mr_form<HMAT_STORE_BF16>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
     return launch_mr_form<HMAT_STORE_FP32>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
 }
 
