@@ -77,11 +77,25 @@ typedef struct hmat_block_desc {
     int64_t ldb;
 } hmat_block_desc;
 
+/* Option flags (hmat_options.flags).
+ *
+ * HMAT_FLAG_FP64_ACCUM -- accuracy-check mode for the output accumulation of
+ * the GEMV form (remark closing Sec. 4.1): every product of a stored factor
+ * with a vector entry, every partial sum of V^T x, every z vector, the sum
+ * over levels and the dense near field, and alpha * (...) + beta * y are
+ * evaluated in FP64 on the device; y is rounded to FP32 once, at the store.
+ * Products of the dequantised factors with FP32 vector entries are exact in
+ * FP64, so the result differs from an exact evaluation of Eq. (2.4) over the
+ * dequantised factors only by FP64 rounding and that final rounding. The mode
+ * always uses the single-vector kernels (one pass per right-hand side, for
+ * any max_nrhs) and is meant for checking, not for speed. */
+#define HMAT_FLAG_FP64_ACCUM 1
+
 typedef struct hmat_options {
     int32_t storage;        /* hmat_storage */
     int32_t max_nrhs;       /* largest nrhs hmat_matvec will be called with, >= 1 */
     int32_t device;         /* HIP device ordinal the data lives on */
-    int32_t flags;          /* must be 0 */
+    int32_t flags;          /* 0 or HMAT_FLAG_FP64_ACCUM; other bits give INVALID_ARG */
 } hmat_options;
 
 typedef struct hmat_info {
@@ -96,6 +110,8 @@ typedef struct hmat_info {
     int64_t workspace_bytes;     /* partial sums and z vectors */
     int32_t storage;
     int32_t max_nrhs;
+    int32_t flags;               /* the flags the handle was created with */
+    int32_t reserved;
 } hmat_info;
 
 typedef struct hmat_handle *hmat_t;
@@ -114,7 +130,8 @@ typedef struct hmat_handle *hmat_t;
  * the leaves, a duplicate, or a missing pair); UNSUPPORTED (leaves at mixed
  * depths, blocks between non-siblings as under standard admissibility, a
  * dense block between non-leaves, a low-rank block between leaves, a chunk
- * whose vector operand exceeds the kernel's LDS budget); NOMEM; DEVICE.
+ * whose vector operand exceeds the kernel's LDS budget -- 16384 FP32 values,
+ * or 8192 FP64 values under HMAT_FLAG_FP64_ACCUM); NOMEM; DEVICE.
  *
  * Ownership: all inputs are deep-copied and re-laid-out; the handle owns its
  * device memory until hmat_destroy. On failure *out is set to NULL and

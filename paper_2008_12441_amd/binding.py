@@ -27,6 +27,8 @@ HMAT_STORE_FP16_SCALED = 1
 HMAT_STORE_BF16 = 2
 STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED, "bf16": HMAT_STORE_BF16}
 
+HMAT_FLAG_FP64_ACCUM = 1
+
 HMAT_NUM_PHASES = 3
 
 
@@ -51,7 +53,8 @@ class hmat_info(ctypes.Structure):
                 ("num_dense_blocks", ctypes.c_int64), ("num_lowrank_blocks", ctypes.c_int64),
                 ("stored_elements", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("device_factor_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("storage", ctypes.c_int32), ("max_nrhs", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -204,9 +207,10 @@ def hmat_probe_bandwidth(src_ptr: int, dst_ptr: int, nbytes: int, mode: int, str
 class HMatrix:
     """Owner of one handle; matvec takes torch CUDA tensors (n x k, column-major or a vector)."""
 
-    def __init__(self, tree_desc, blocks, *, storage="fp32", max_nrhs=1, device=0):
+    def __init__(self, tree_desc, blocks, *, storage="fp32", max_nrhs=1, device=0, fp64_accum=False):
         st = STORAGE[storage] if isinstance(storage, str) else int(storage)
-        self.handle = hmat_create(tree_desc, blocks, storage=st, max_nrhs=max_nrhs, device=device)
+        flags = HMAT_FLAG_FP64_ACCUM if fp64_accum else 0
+        self.handle = hmat_create(tree_desc, blocks, storage=st, max_nrhs=max_nrhs, device=device, flags=flags)
         self.info = hmat_get_info(self.handle)
         self.n = int(self.info["n"])
 

@@ -324,7 +324,7 @@ struct HostPlan {
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
-                       int32_t storage, HostPlan &hp) {
+                       int32_t storage, int32_t acc_bytes, HostPlan &hp) {
     hp.vw = storage == HMAT_STORE_FP32 ? 4 : 8;
     hp.bf16 = storage == HMAT_STORE_BF16;
     const int32_t vw = hp.vw;
@@ -479,9 +479,10 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
     hp.ud_elems = ud_cur;
     hp.part_floats = part_cur;
     hp.lds_floats = max_lds;
-    if (max_lds > hmat::kMaxLdsFloats)
+    if ((int64_t)max_lds * acc_bytes > hmat::kMaxLdsBytes)
         return fail(HMAT_ERR_UNSUPPORTED, "a chunk's vector operand (" + std::to_string(max_lds) +
-                                              " floats) exceeds the U-phase LDS budget");
+                                              " values of " + std::to_string(acc_bytes) +
+                                              " bytes) exceeds the U-phase LDS budget");
     if (hp.part_floats >= INT32_MAX || hp.zg_floats >= INT32_MAX)
         return fail(HMAT_ERR_UNSUPPORTED, "workspace too large");
 
@@ -1096,7 +1097,9 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
         return fail(HMAT_ERR_INVALID_ARG, "unknown storage form");
     if (opts->max_nrhs < 1) return fail(HMAT_ERR_INVALID_ARG, "max_nrhs must be >= 1");
     if (opts->device < 0) return fail(HMAT_ERR_INVALID_ARG, "device must be >= 0");
-    if (opts->flags != 0) return fail(HMAT_ERR_INVALID_ARG, "flags must be 0");
+    if ((opts->flags & ~HMAT_FLAG_FP64_ACCUM) != 0) return fail(HMAT_ERR_INVALID_ARG, "unknown option flags");
+    const bool fp64 = (opts->flags & HMAT_FLAG_FP64_ACCUM) != 0;
+    const int32_t acc_bytes = fp64 ? 8 : 4;
     Tree t;
     hmat_status s = analyse_tree(tree, t);
     if (s != HMAT_OK) return s;
@@ -1105,9 +1108,9 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     if (s != HMAT_OK) return s;
     HostPlan hp;
     HostPlanMR hpm;
-    h->mr = opts->max_nrhs > 1;
+    h->mr = opts->max_nrhs > 1 && !fp64;
     s = h->mr ? build_plan_mr(t, st, blocks, nb, opts->storage, opts->max_nrhs, hpm)
-              : build_plan(t, st, blocks, nb, opts->storage, hp);
+              : build_plan(t, st, blocks, nb, opts->storage, acc_bytes, hp);
     if (s != HMAT_OK) return s;
 
     h->device = opts->device;
@@ -1134,9 +1137,10 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     const int64_t esz = opts->storage == HMAT_STORE_FP32 ? 4 : 2;
     in.factor_bytes = elems * esz + (opts->storage == HMAT_STORE_FP16_SCALED ? 4 * (nd + 2 * nl) : 0);
     in.device_factor_bytes = (hp.v_elems + hp.ud_elems) * esz;
-    in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * 4;
+    in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * acc_bytes;
     in.storage = opts->storage;
     in.max_nrhs = opts->max_nrhs;
+    in.flags = opts->flags;
 
     if (h->mr) {
         if (opts->storage != HMAT_STORE_FP32) return upload_mr<uint16_t>(h, t, st, blocks, hpm);
@@ -1145,6 +1149,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
 
     DevPlan &p = h->plan;
     p.storage = opts->storage;
+    p.fp64 = fp64 ? 1 : 0;
     p.num_chunks = (int32_t)hp.chunks.size();
     p.num_vtiles = (int32_t)hp.vtiles.size();
     p.num_z1 = (int32_t)hp.z1.size();
@@ -1154,11 +1159,11 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     p.max_leaf_rows = hp.max_leaf_rows;
 
     void *ws = nullptr;
-    if ((s = dev_alloc(h, hp.part_floats * 4, &ws)) != HMAT_OK) return s;
-    p.part = static_cast<float *>(ws);
-    if ((s = dev_alloc(h, (hp.zg_floats + hp.slice_floats) * 4, &ws)) != HMAT_OK) return s;
-    p.zg = static_cast<float *>(ws);
-    p.slice = p.zg + hp.zg_floats;
+    if ((s = dev_alloc(h, hp.part_floats * acc_bytes, &ws)) != HMAT_OK) return s;
+    p.part = ws;
+    if ((s = dev_alloc(h, (hp.zg_floats + hp.slice_floats) * acc_bytes, &ws)) != HMAT_OK) return s;
+    p.zg = ws;
+    p.slice = static_cast<char *>(ws) + hp.zg_floats * acc_bytes;
     if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
     {
         std::vector<int32_t> pb(hp.chunks.size());

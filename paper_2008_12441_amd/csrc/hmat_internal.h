@@ -35,7 +35,7 @@
 namespace hmat {
 
 constexpr int kWave = 64;
-constexpr int kMaxLdsFloats = 16384;  // U-phase vector operand budget per chunk (64 KiB)
+constexpr int kMaxLdsBytes = 65536;   // U-phase vector operand budget per chunk (64 KiB)
 
 struct ChunkMeta {
     int32_t row_begin;   // first global row
@@ -89,6 +89,8 @@ struct ZItem2 {          // stage 2: sum of slices of a block spanning many chun
 
 struct DevPlan {
     int32_t storage;          // hmat_storage
+    int32_t fp64;             // HMAT_FLAG_FP64_ACCUM: part, slice, zg and all sums in double
+    int32_t pad_;
     int32_t num_chunks;
     int32_t num_vtiles;
     int32_t num_z1;
@@ -98,9 +100,9 @@ struct DevPlan {
     int32_t max_leaf_rows;
     const void *V;            // float or _Float16
     const void *UD;
-    float *part;
-    float *slice;
-    float *zg;
+    void *part;               // float, or double in FP64 mode (offsets count elements)
+    void *slice;
+    void *zg;
     const ChunkMeta *chunks;
     const int32_t *pbase;     // per chunk: offset of its partial sums (= chunks[c].part_base)
     const ZSeg *zsegs;

@@ -13,6 +13,10 @@
 //              in LDS, and writes y once.
 // All streams are HBM-bound (two flops per stored element); the layouts make
 // every wave-level load a contiguous 1 KiB.
+//
+// Every kernel is templated on its accumulator type: float for the product
+// itself, double for the accuracy-check mode, where partial sums, z, the LDS
+// operand and the row sums are all FP64 and y is rounded to FP32 at the store.
 #include <hip/hip_runtime.h>
 
 #include "hmat.h"
@@ -84,7 +88,7 @@ __device__ inline int wave_id_in_grid(int waves_per_block) {
 // accumulates sum_i V[i, col] x[i] over the chunk's rows. x is uniform across
 // the wave, so its loads are scalar.
 // ---------------------------------------------------------------------------
-template <int STORE>
+template <int STORE, class Acc>
 __global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restrict__ x) {
     using F = Form<STORE>;
     constexpr int VW = F::VW;
@@ -96,9 +100,9 @@ __global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restri
     const float *__restrict__ xc = x + p.chunks[vt.chunk].row_begin;
     const typename F::Vec *tile =
         reinterpret_cast<const typename F::Vec *>(static_cast<const typename F::Elem *>(p.V) + vt.off) + lane;
-    float acc[VW];
+    Acc acc[VW];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) acc[e] = 0.0f;
+    for (int e = 0; e < VW; ++e) acc[e] = 0;
     const int nfull = rows / VW;
     int q = 0;
     for (; q + kVUnroll <= nfull; q += kVUnroll) {
@@ -108,25 +112,25 @@ __global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restri
 #pragma unroll
         for (int u = 0; u < kVUnroll; ++u)
 #pragma unroll
-            for (int e = 0; e < VW; ++e) acc[e] = fmaf(v[u][e], xc[(q + u) * VW + e], acc[e]);
+            for (int e = 0; e < VW; ++e) acc[e] = fma((Acc)v[u][e], (Acc)xc[(q + u) * VW + e], acc[e]);
     }
     for (; q < nfull; ++q) {
         float v[VW];
         F::load(tile + (int64_t)q * kWave, v);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] = fmaf(v[e], xc[q * VW + e], acc[e]);
+        for (int e = 0; e < VW; ++e) acc[e] = fma((Acc)v[e], (Acc)xc[q * VW + e], acc[e]);
     }
     if (q * VW < rows) {  // ragged last vector: rows past the chunk hold zeros in V
         float v[VW];
         F::load(tile + (int64_t)q * kWave, v);
 #pragma unroll
         for (int e = 0; e < VW; ++e)
-            if (q * VW + e < rows) acc[e] = fmaf(v[e], xc[q * VW + e], acc[e]);
+            if (q * VW + e < rows) acc[e] = fma((Acc)v[e], (Acc)xc[q * VW + e], acc[e]);
     }
-    float s = 0.0f;
+    Acc s = 0;
 #pragma unroll
     for (int e = 0; e < VW; ++e) s += acc[e];
-    p.part[vt.pout + lane] = s;
+    static_cast<Acc *>(p.part)[vt.pout + lane] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -135,44 +139,48 @@ __global__ __launch_bounds__(256) void k_vphase(DevPlan p, const float *__restri
 // source box. Items of boxes that span more chunks write slices that stage 2
 // adds up, also in order, so the result is deterministic.
 // ---------------------------------------------------------------------------
+template <class Acc>
 __global__ __launch_bounds__(256) void k_zsum1(DevPlan p) {
     const int w = wave_id_in_grid(4);
     if (w >= p.num_z1) return;
     const int lane = threadIdx.x & 63;
     const ZItem it = p.z1[w];
     const int32_t *pb = p.pbase + it.chunk0;
+    Acc *zg = static_cast<Acc *>(p.zg);
     for (int k = lane; k < it.rank; k += kWave) {
         // eight independent partial sums keep eight loads in flight; they are
         // combined in a fixed order, so the result stays deterministic
-        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        const float *src = p.part + it.vcol + k;
+        Acc a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const Acc *src = static_cast<const Acc *>(p.part) + it.vcol + k;
         int c = 0;
         for (; c + 8 <= it.nchunks; c += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) a[u] += src[pb[c + u]];
         }
         for (; c < it.nchunks; ++c) a[0] += src[pb[c]];
-        const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-        p.zg[it.dst + k] = s * it.scale;
+        const Acc s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        zg[it.dst + k] = s * (Acc)it.scale;
     }
 }
 
+template <class Acc>
 __global__ __launch_bounds__(256) void k_zsum2(DevPlan p) {
     const int w = wave_id_in_grid(4);
     if (w >= p.num_z2) return;
     const int lane = threadIdx.x & 63;
     const ZItem2 it = p.z2[w];
+    Acc *zg = static_cast<Acc *>(p.zg);
     for (int k = lane; k < it.rank; k += kWave) {
-        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        const float *src = p.zg + it.src + k;
+        Acc a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const Acc *src = zg + it.src + k;
         int c = 0;
         for (; c + 8 <= it.nslices; c += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) a[u] += src[(c + u) * it.rank];
         }
         for (; c < it.nslices; ++c) a[0] += src[c * it.rank];
-        const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-        p.zg[it.dst + k] = s * it.scale;
+        const Acc s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        zg[it.dst + k] = s * (Acc)it.scale;
     }
 }
 
@@ -182,13 +190,13 @@ __global__ __launch_bounds__(256) void k_zsum2(DevPlan p) {
 // is staged in LDS; each wave takes 64-row tiles, one row per lane, and reads
 // VW columns per 16-byte load with the operand broadcast from LDS.
 // ---------------------------------------------------------------------------
-template <int STORE>
-__device__ inline float dot_range(const typename Form<STORE>::Vec *base, const float *vec, int q0, int q1) {
+template <int STORE, class Acc>
+__device__ inline Acc dot_range(const typename Form<STORE>::Vec *base, const Acc *vec, int q0, int q1) {
     using F = Form<STORE>;
     constexpr int VW = F::VW;
-    float a[VW];
+    Acc a[VW];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) a[e] = 0.0f;
+    for (int e = 0; e < VW; ++e) a[e] = 0;
     int q = q0;
     for (; q + kUUnroll <= q1; q += kUUnroll) {
         float v[kUUnroll][VW];
@@ -197,40 +205,42 @@ __device__ inline float dot_range(const typename Form<STORE>::Vec *base, const f
 #pragma unroll
         for (int u = 0; u < kUUnroll; ++u)
 #pragma unroll
-            for (int e = 0; e < VW; ++e) a[e] = fmaf(v[u][e], vec[(q + u) * VW + e], a[e]);
+            for (int e = 0; e < VW; ++e) a[e] = fma((Acc)v[u][e], vec[(q + u) * VW + e], a[e]);
     }
     for (; q < q1; ++q) {
         float v[VW];
         F::load(base + (int64_t)q * kWave, v);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) a[e] = fmaf(v[e], vec[q * VW + e], a[e]);
+        for (int e = 0; e < VW; ++e) a[e] = fma((Acc)v[e], vec[q * VW + e], a[e]);
     }
-    float s = 0.0f;
+    Acc s = 0;
 #pragma unroll
     for (int e = 0; e < VW; ++e) s += a[e];
     return s;
 }
 
-template <int STORE>
+template <int STORE, class Acc>
 __global__ __launch_bounds__(256) void k_uphase(DevPlan p, const float *__restrict__ x, float *__restrict__ y,
                                                 float alpha, float beta) {
     using F = Form<STORE>;
     constexpr int VW = F::VW;
-    extern __shared__ float vec[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Acc *vec = reinterpret_cast<Acc *>(lds_raw);
+    const Acc *zg = static_cast<const Acc *>(p.zg);
     const int c = blockIdx.x;
     const ChunkMeta m = p.chunks[c];
     const int tid = threadIdx.x;
     int pos = 0;
     for (int l = 0; l < p.num_levels; ++l) {
         const ZSeg zs = p.zsegs[m.zseg_base + l];
-        for (int j = tid; j < zs.len; j += 256) vec[pos + j] = p.zg[zs.off + j];
+        for (int j = tid; j < zs.len; j += 256) vec[pos + j] = zg[zs.off + j];
         pos += zs.len;
     }
-    for (int j = pos + tid; j < m.nq_lr * VW; j += 256) vec[j] = 0.0f;
+    for (int j = pos + tid; j < m.nq_lr * VW; j += 256) vec[j] = 0;
     pos = m.nq_lr * VW;
     for (int s = 0; s < m.nleaf; ++s) {
         const DSeg ds = p.dsegs[m.dseg_base + s];
-        for (int j = tid; j < ds.nq * VW; j += 256) vec[pos + j] = j < ds.rows ? x[ds.row_begin + j] : 0.0f;
+        for (int j = tid; j < ds.nq * VW; j += 256) vec[pos + j] = j < ds.rows ? (Acc)x[ds.row_begin + j] : (Acc)0;
         pos += ds.nq * VW;
     }
     __syncthreads();
@@ -242,25 +252,25 @@ __global__ __launch_bounds__(256) void k_uphase(DevPlan p, const float *__restri
             reinterpret_cast<const typename F::Vec *>(static_cast<const typename F::Elem *>(p.UD) + m.ud_off) +
             (int64_t)tile * m.nq * kWave + lane;
         const int row = tile * kWave + lane;
-        float acc = dot_range<STORE>(base, vec, 0, m.nq_lr);
+        Acc acc = dot_range<STORE, Acc>(base, vec, 0, m.nq_lr);
         int tleaf = 0;
         if (STORE == HMAT_STORE_FP16_SCALED)
             while (tleaf + 1 < m.nleaf && m.row_begin + row >= p.dsegs[m.dseg_base + tleaf + 1].row_begin) ++tleaf;
         int q = m.nq_lr;
         for (int s = 0; s < m.nleaf; ++s) {
             const int nq = p.dsegs[m.dseg_base + s].nq;
-            const float part = dot_range<STORE>(base, vec, q, q + nq);
+            const Acc part = dot_range<STORE, Acc>(base, vec, q, q + nq);
             if (STORE == HMAT_STORE_FP16_SCALED)
-                acc = fmaf(p.dscale[m.dscale_base + tleaf * m.nleaf + s], part, acc);
+                acc = fma((Acc)p.dscale[m.dscale_base + tleaf * m.nleaf + s], part, acc);
             else
                 acc += part;
             q += nq;
         }
         if (row < m.rows) {
             float *yp = y + m.row_begin + row;
-            float v = alpha * acc;
-            if (beta != 0.0f) v = fmaf(beta, *yp, v);
-            *yp = v;
+            Acc v = (Acc)alpha * acc;
+            if (beta != 0.0f) v = fma((Acc)beta, (Acc)*yp, v);
+            *yp = (float)v;  // the only rounding to FP32 of the output
         }
     }
 }
@@ -297,36 +307,59 @@ __global__ __launch_bounds__(256) void k_probe_copy(const f32x4 *__restrict__ sr
 
 }  // namespace
 
-int launch_vphase(const DevPlan &p, const float *x, void *stream) {
+template <class Acc>
+static void launch_vphase_acc(const DevPlan &p, const float *x, hipStream_t st) {
     const int blocks = (p.num_vtiles + 3) / 4;
     if (p.storage == HMAT_STORE_FP16_SCALED)
-        hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP16_SCALED>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+        hipLaunchKernelGGL((k_vphase<HMAT_STORE_FP16_SCALED, Acc>), dim3(blocks), dim3(256), 0, st, p, x);
     else if (p.storage == HMAT_STORE_BF16)
-        hipLaunchKernelGGL(k_vphase<HMAT_STORE_BF16>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+        hipLaunchKernelGGL((k_vphase<HMAT_STORE_BF16, Acc>), dim3(blocks), dim3(256), 0, st, p, x);
     else
-        hipLaunchKernelGGL(k_vphase<HMAT_STORE_FP32>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, p, x);
+        hipLaunchKernelGGL((k_vphase<HMAT_STORE_FP32, Acc>), dim3(blocks), dim3(256), 0, st, p, x);
+}
+
+int launch_vphase(const DevPlan &p, const float *x, void *stream) {
+    if (p.fp64)
+        launch_vphase_acc<double>(p, x, (hipStream_t)stream);
+    else
+        launch_vphase_acc<float>(p, x, (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+template <class Acc>
+static int launch_zfinish_acc(const DevPlan &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_zsum1<Acc>, dim3((p.num_z1 + 3) / 4), dim3(256), 0, st, p);
+    int e = (int)hipGetLastError();
+    if (e != 0 || p.num_z2 == 0) return e;
+    hipLaunchKernelGGL(k_zsum2<Acc>, dim3((p.num_z2 + 3) / 4), dim3(256), 0, st, p);
     return (int)hipGetLastError();
 }
 
 int launch_zfinish(const DevPlan &p, void *stream) {
-    hipLaunchKernelGGL(k_zsum1, dim3((p.num_z1 + 3) / 4), dim3(256), 0, (hipStream_t)stream, p);
-    int e = (int)hipGetLastError();
-    if (e != 0 || p.num_z2 == 0) return e;
-    hipLaunchKernelGGL(k_zsum2, dim3((p.num_z2 + 3) / 4), dim3(256), 0, (hipStream_t)stream, p);
-    return (int)hipGetLastError();
+    return p.fp64 ? launch_zfinish_acc<double>(p, (hipStream_t)stream)
+                  : launch_zfinish_acc<float>(p, (hipStream_t)stream);
+}
+
+template <class Acc>
+static void launch_uphase_acc(const DevPlan &p, const float *x, float *y, float alpha, float beta,
+                              hipStream_t st) {
+    const size_t lds = (size_t)p.lds_floats * sizeof(Acc);
+    if (p.storage == HMAT_STORE_FP16_SCALED)
+        hipLaunchKernelGGL((k_uphase<HMAT_STORE_FP16_SCALED, Acc>), dim3(p.num_chunks), dim3(256), lds, st, p, x,
+                           y, alpha, beta);
+    else if (p.storage == HMAT_STORE_BF16)
+        hipLaunchKernelGGL((k_uphase<HMAT_STORE_BF16, Acc>), dim3(p.num_chunks), dim3(256), lds, st, p, x, y,
+                           alpha, beta);
+    else
+        hipLaunchKernelGGL((k_uphase<HMAT_STORE_FP32, Acc>), dim3(p.num_chunks), dim3(256), lds, st, p, x, y,
+                           alpha, beta);
 }
 
 int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float beta, void *stream) {
-    const size_t lds = (size_t)p.lds_floats * sizeof(float);
-    if (p.storage == HMAT_STORE_FP16_SCALED)
-        hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP16_SCALED>, dim3(p.num_chunks), dim3(256), lds,
-                           (hipStream_t)stream, p, x, y, alpha, beta);
-    else if (p.storage == HMAT_STORE_BF16)
-        hipLaunchKernelGGL(k_uphase<HMAT_STORE_BF16>, dim3(p.num_chunks), dim3(256), lds, (hipStream_t)stream,
-                           p, x, y, alpha, beta);
+    if (p.fp64)
+        launch_uphase_acc<double>(p, x, y, alpha, beta, (hipStream_t)stream);
     else
-        hipLaunchKernelGGL(k_uphase<HMAT_STORE_FP32>, dim3(p.num_chunks), dim3(256), lds, (hipStream_t)stream, p,
-                           x, y, alpha, beta);
+        launch_uphase_acc<float>(p, x, y, alpha, beta, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 

@@ -12,9 +12,9 @@ def descriptors(data):
                                data.blocks.rank, data.pool, data.off_a, data.off_b)
 
 
-def create(data, storage="fp32", max_nrhs=1):
+def create(data, storage="fp32", max_nrhs=1, fp64_accum=False):
     tree, blocks, keep = descriptors(data)
-    return hm.HMatrix(tree, blocks, storage=storage, max_nrhs=max_nrhs)
+    return hm.HMatrix(tree, blocks, storage=storage, max_nrhs=max_nrhs, fp64_accum=fp64_accum)
 
 
 def gpu_matvec(h, x, *, alpha=1.0, beta=0.0, y0=None, ld_pad=0):
@@ -56,3 +56,20 @@ def assert_close(y, ref, rel_tol, elem_tol=None):
         worst = np.max(np.abs(y - ref) / rms[None, :])
         assert worst <= elem_tol, f"element error {worst:.3e} x RMS > {elem_tol:.1e}"
     return float(errs.max())
+
+
+def assert_fp32_rounding_of(y, ref, min_exact=0.99):
+    """y (FP32 values) is ref (FP64) rounded to FP32, up to one FP32 unit in the
+    last place per element; at least ``min_exact`` of the elements round the same
+    way (they differ only where ref lies within FP64 roundoff of a midpoint)."""
+    assert np.isfinite(y).all(), "non-finite output"
+    y32 = np.asarray(y, np.float64).astype(np.float32)
+    assert np.array_equal(y32.astype(np.float64), np.asarray(y, np.float64)), "y holds non-FP32 values"
+    r32 = np.asarray(ref, np.float64).astype(np.float32)
+    ulp = np.maximum(np.spacing(np.abs(r32)), np.spacing(np.abs(y32))).astype(np.float64)
+    diff = np.abs(y32.astype(np.float64) - r32.astype(np.float64))
+    worst = float(np.max(diff / ulp)) if diff.size else 0.0
+    assert worst <= 1.0, f"an element is {worst:.1f} FP32 ulp from the rounded reference"
+    exact = float(np.mean(diff == 0)) if diff.size else 1.0
+    assert exact >= min_exact, f"only {exact:.4f} of the elements are the rounded reference"
+    return exact

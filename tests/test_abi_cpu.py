@@ -70,6 +70,8 @@ def test_null_and_option_errors(small):
     _expect(_create_status(tree, blocks, storage=7), 1, "storage")
     _expect(_create_status(tree, blocks, max_nrhs=0), 1, "max_nrhs")
     _expect(_create_status(tree, blocks, flags=3), 1, "flags")
+    _expect(_create_status(tree, blocks, flags=2), 1, "flags")
+    _expect(_create_status(tree, blocks, flags=-1), 1, "flags")
     _expect(_create_status(tree, blocks, device=-1), 1, "device")
 
 
@@ -195,3 +197,26 @@ def test_degenerate_trees_validate():
         tr, bl, keep = descriptors(data)
         st, msg = _create_status(tr, bl)
         assert st in (0, 6), msg
+
+
+def test_fp64_accum_lds_budget():
+    """A chunk whose U-phase operand fits the LDS budget in FP32 (8500 values,
+    34 KB) but not in FP64 (68 KB) is UNSUPPORTED only in the FP64 mode; the
+    check runs before any device call. Factors all alias one zero buffer."""
+    par = np.array([-1, 0, 0, 1, 1, 2, 2], np.int32)
+    beg = np.array([0, 0, 6000, 0, 3000, 6000, 9000], np.int64)
+    end = np.array([12000, 6000, 12000, 3000, 6000, 9000, 12000], np.int64)
+    tree = hm.make_tree_desc(par, beg, end)
+    buf = np.zeros(6000 * 2500, np.float32)
+    recs = [(1, 2, 2500), (2, 1, 2500)]
+    for p in (1, 2):
+        kids = [3, 4] if p == 1 else [5, 6]
+        recs += [(t, s_, 0) for t in kids for s_ in kids]
+    blocks = np.zeros(len(recs), dtype=hm.BLOCK_DTYPE)
+    for i, (t, s_, r) in enumerate(recs):
+        size = 6000 if r else 3000
+        blocks[i] = (t, s_, r, 0, buf.ctypes.data, size, buf.ctypes.data if r else 0, size if r else 0)
+    st, msg = _create_status(tree, blocks, flags=1)
+    assert st == 4 and "LDS" in msg, (st, msg)
+    st, msg = _create_status(tree, blocks, flags=0)
+    assert st != 4, msg

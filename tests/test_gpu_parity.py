@@ -15,7 +15,7 @@ import pytest
 import oracle
 from oracle.quant import dequantised
 from hmat_inputs import build_tree, make_hmatrix, make_rhs, uniform_tree
-from hmat_testlib import assert_close, create, gpu_matvec
+from hmat_testlib import assert_close, assert_fp32_rounding_of, create, gpu_matvec
 
 pytestmark = pytest.mark.gpu
 
@@ -170,6 +170,16 @@ def test_c2_full_size_fp32(c2_random):
     with create(data) as h:
         y = gpu_matvec(h, x)
     assert_close(y, ref, FP32_TOL, ELEM_TOL)
+
+
+def test_c2_full_size_fp64_accum(c2_random):
+    data, prep = c2_random
+    _log("case c2 fp32 storage, FP64 accumulation, full size")
+    x = make_rhs(data.n, 1, 1002)
+    ref = oracle.oracle_matvec(prep, x)
+    with create(data, fp64_accum=True) as h:
+        y = gpu_matvec(h, x)
+    assert_fp32_rounding_of(y, ref)
 
 
 def test_c2_full_size_fp16(c2_random):
