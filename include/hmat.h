@@ -181,6 +181,93 @@ hmat_status hmat_get_timing(hmat_t h, double ms[HMAT_NUM_PHASES], int64_t *calls
 hmat_status hmat_probe_bandwidth(const void *src, void *dst, int64_t bytes, int32_t mode,
                                  void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched product: many independent H-matrices (each built by hmat_create)
+ * applied by one persistent kernel launch, replayed as a HIP graph.
+ *
+ * Each member's product is split into items (pieces of the source-side
+ * products, of the partial reduction and of the target-side products, Sec.
+ * 4.1, Steps 1-5) held in one queue in stage order; the kernel's workgroups
+ * take items from the queue, and an item waits on its own member's earlier
+ * stage through a completion counter. Under weak admissibility every box of a
+ * level carries the same number of blocks (Sec. 3.2), so an item's work is
+ * its byte count, which the queue is sorted by.
+ * ------------------------------------------------------------------------ */
+typedef struct hmat_batch_handle *hmat_batch_t;
+
+typedef struct hmat_batch_options {
+    int32_t use_graph;      /* 1: each call replays a HIP graph of (counter clear, persistent kernel);
+                               0: the two kernels are launched directly on the caller's stream */
+    int32_t wg_per_cu;      /* persistent workgroups per compute unit; 0 = as many as fit */
+    int32_t order;          /* queue order inside each stage band: 0 = largest item first,
+                               1 = member by member (largest member first) */
+    int32_t spin_limit;     /* polls before a dependency wait gives up and flags an error; 0 = 2^20 */
+} hmat_batch_options;
+
+typedef struct hmat_batch_info {
+    int32_t count;          /* members */
+    int32_t num_items;      /* queue length */
+    int32_t grid;           /* persistent workgroups launched */
+    int32_t wg_per_cu;
+    int32_t max_wg_per_cu;  /* most that can be resident */
+    int32_t order;
+    int32_t use_graph;
+    int32_t reserved;
+    int64_t lds_bytes;      /* dynamic LDS per workgroup */
+    int64_t item_bytes;     /* factor bytes the items stream per call, layout padding included */
+} hmat_batch_info;
+
+/* Build a batch over `count` live handles. nrhs[i] is the number of
+ * right-hand sides member i is applied to: 1 for a handle created with
+ * max_nrhs == 1 (single-vector kernels); 1 <= nrhs[i] <= min(16, max_nrhs) for
+ * one created with max_nrhs > 1 (MFMA kernels, one tile of 16 columns).
+ * Members must be distinct, live on one device, share one storage form and
+ * have no flags. A batch uses its members' device workspaces: while it exists
+ * the members cannot be destroyed (hmat_destroy gives INVALID_ARG), and a
+ * member must not run hmat_matvec concurrently with the batch. opts may be
+ * NULL (defaults: graph on, as many workgroups as fit, largest item first).
+ *
+ * Errors: INVALID_ARG; UNSUPPORTED (a multi-RHS member whose chunks have more
+ * than 64 target-side segments); NOMEM; DEVICE. */
+hmat_status hmat_batch_create(const hmat_t *members, int32_t count, const int32_t *nrhs,
+                              const hmat_batch_options *opts, hmat_batch_t *out);
+
+/* y_i = alpha K_i x_i + beta y_i for every member i. x[i] and y[i] are device
+ * pointers (n_i x nrhs[i], column-major, leading dimensions ldx[i], ldy[i] >=
+ * n_i); the pointer and leading-dimension arrays are host arrays read during
+ * the call. No x[i] may overlap any y[j], and the y[i] must not overlap each
+ * other. Asynchronous on `stream`; when the pointers differ from the last
+ * call's, they are copied to the device on `stream` first. One batch owns one
+ * set of counters: calls on the same batch must be ordered on one stream.
+ * Errors: INVALID_ARG; DEVICE (launch failure). */
+hmat_status hmat_batch_matvec(hmat_batch_t b, float alpha, const float *const *x, const int64_t *ldx, float beta,
+                              float *const *y, const int64_t *ldy, void *stream);
+
+/* Wait for `stream` and report the last batched product's status: DEVICE
+ * when one of its dependency waits hit the poll limit (its y is then not
+ * valid). */
+hmat_status hmat_batch_sync(hmat_batch_t b, void *stream);
+
+/* Change the launch options (rebuilds the queue and the graph). */
+hmat_status hmat_batch_set_options(hmat_batch_t b, const hmat_batch_options *opts);
+hmat_status hmat_batch_get_info(hmat_batch_t b, hmat_batch_info *info);
+
+/* Autotuner: time every candidate (wg_per_cu in {1, 2, 3, 4, 6, 8} up to the
+ * resident maximum, order in {0, 1}) on the given operands, `reps` timed
+ * calls each after two untimed ones, and keep the fastest. With a non-NULL
+ * cache_path, a JSON file of earlier results keyed by a hash of the device and
+ * the members' shapes is read first (a hit skips the timing) and updated
+ * after. The chosen options are applied to the batch and, when `chosen` is
+ * not NULL, returned there. The calls overwrite y. Synchronises `stream`.
+ * Errors: INVALID_ARG; DEVICE; NOMEM. */
+hmat_status hmat_batch_autotune(hmat_batch_t b, float alpha, const float *const *x, const int64_t *ldx,
+                                float beta, float *const *y, const int64_t *ldy, void *stream,
+                                const char *cache_path, int32_t reps, hmat_batch_options *chosen);
+
+/* Release the batch (not its members). NULL is a no-op. Work queued on a
+ * stream that still uses the batch must have completed. */
+hmat_status hmat_batch_destroy(hmat_batch_t b);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *hmat_last_error(void);
 

@@ -5,15 +5,18 @@ in hand-written HIP kernels behind the C ABI of ``include/hmat.h``; this
 package is the thin Python binding of that library (``binding``) and its
 build step (``_build``).
 """
-from .binding import (BLOCK_DTYPE, EXPORTED, HMAT_STORE_FP16_SCALED, HMAT_STORE_FP32, LIB_PATH, STORAGE,
-                      HMatrix, HmatError, hmat_create, hmat_destroy, hmat_get_info, hmat_get_timing,
-                      hmat_last_error, hmat_matvec, hmat_probe_bandwidth, hmat_set_timing,
-                      hmat_status_string, load_library, make_block_array, make_descriptors,
-                      make_tree_desc)
+from .binding import (BLOCK_DTYPE, EXPORTED, HMAT_FLAG_FP64_ACCUM, HMAT_STORE_BF16, HMAT_STORE_FP16_SCALED,
+                      HMAT_STORE_FP32, LIB_PATH, STORAGE, HBatch, HMatrix, HmatError, hmat_batch_autotune,
+                      hmat_batch_create, hmat_batch_destroy, hmat_batch_get_info, hmat_batch_matvec,
+                      hmat_batch_set_options, hmat_batch_sync, hmat_create, hmat_destroy, hmat_get_info,
+                      hmat_get_timing, hmat_last_error, hmat_matvec, hmat_probe_bandwidth, hmat_set_timing,
+                      hmat_status_string, load_library, make_block_array, make_descriptors, make_tree_desc)
 
 __all__ = [
-    "BLOCK_DTYPE", "EXPORTED", "HMAT_STORE_FP16_SCALED", "HMAT_STORE_FP32", "LIB_PATH", "STORAGE", "HMatrix",
-    "HmatError", "hmat_create", "hmat_destroy", "hmat_get_info", "hmat_get_timing", "hmat_last_error",
-    "hmat_matvec", "hmat_probe_bandwidth", "hmat_set_timing", "hmat_status_string", "load_library",
-    "make_block_array", "make_descriptors", "make_tree_desc",
+    "BLOCK_DTYPE", "EXPORTED", "HMAT_FLAG_FP64_ACCUM", "HMAT_STORE_BF16", "HMAT_STORE_FP16_SCALED",
+    "HMAT_STORE_FP32", "LIB_PATH", "STORAGE", "HBatch", "HMatrix", "HmatError", "hmat_batch_autotune",
+    "hmat_batch_create", "hmat_batch_destroy", "hmat_batch_get_info", "hmat_batch_matvec",
+    "hmat_batch_set_options", "hmat_batch_sync", "hmat_create", "hmat_destroy", "hmat_get_info",
+    "hmat_get_timing", "hmat_last_error", "hmat_matvec", "hmat_probe_bandwidth", "hmat_set_timing",
+    "hmat_status_string", "load_library", "make_block_array", "make_descriptors", "make_tree_desc",
 ]

@@ -16,6 +16,8 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
+HOST_SOURCES = ["hmat_host.cpp", "hmat_batch_host.cpp"]
+HIP_SOURCES = ["hmat_kernels.hip", "hmat_mr_kernels.hip", "hmat_batch.hip"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
               f"-I{ROCM}/include", f"-I{INCLUDE}", f"-I{CSRC}"]
 
@@ -30,17 +32,18 @@ def build(verbose: bool = False) -> str:
     """Compile every source of the library and link it; always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    host_o = os.path.join(BUILD, "hmat_host.o")
-    kern_o = os.path.join(BUILD, "hmat_kernels.o")
-    mr_o = os.path.join(BUILD, "hmat_mr_kernels.o")
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "hmat_host.cpp"), "-o", host_o], verbose)
-    _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, "hmat_kernels.hip"),
-          "-o", kern_o], verbose)
-    _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, "hmat_mr_kernels.hip"),
-          "-o", mr_o], verbose)
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o,
-          kern_o, mr_o, "-o", tmp, "-lpthread"], verbose)
+    _run([os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
+          "-lpthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -66,8 +66,28 @@ BLOCK_DTYPE = np.dtype([("target", np.int32), ("source", np.int32), ("rank", np.
                         ("b", np.uint64), ("ldb", np.int64)], align=True)
 assert BLOCK_DTYPE.itemsize == ctypes.sizeof(hmat_block_desc)
 
+class hmat_batch_options(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class hmat_batch_info(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("num_items", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("max_wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+                ("item_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 EXPORTED = ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
-            "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string")
+            "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string",
+            "hmat_batch_create", "hmat_batch_matvec", "hmat_batch_sync", "hmat_batch_set_options",
+            "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy")
 
 
 class HmatError(RuntimeError):
@@ -106,8 +126,21 @@ def load_library(path: str | None = None):
     lib.hmat_last_error.restype = ctypes.c_char_p
     lib.hmat_status_string.restype = ctypes.c_char_p
     lib.hmat_status_string.argtypes = [ctypes.c_int]
+    pp = ctypes.POINTER(vp)
+    p64 = ctypes.POINTER(i64)
+    lib.hmat_batch_create.argtypes = [pp, i32, ctypes.POINTER(i32), ctypes.POINTER(hmat_batch_options),
+                                      ctypes.POINTER(vp)]
+    lib.hmat_batch_matvec.argtypes = [vp, ctypes.c_float, pp, p64, ctypes.c_float, pp, p64, vp]
+    lib.hmat_batch_sync.argtypes = [vp, vp]
+    lib.hmat_batch_set_options.argtypes = [vp, ctypes.POINTER(hmat_batch_options)]
+    lib.hmat_batch_get_info.argtypes = [vp, ctypes.POINTER(hmat_batch_info)]
+    lib.hmat_batch_autotune.argtypes = [vp, ctypes.c_float, pp, p64, ctypes.c_float, pp, p64, vp,
+                                        ctypes.c_char_p, i32, ctypes.POINTER(hmat_batch_options)]
+    lib.hmat_batch_destroy.argtypes = [vp]
     for name in ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
-                 "hmat_get_timing", "hmat_probe_bandwidth"):
+                 "hmat_get_timing", "hmat_probe_bandwidth", "hmat_batch_create", "hmat_batch_matvec",
+                 "hmat_batch_sync", "hmat_batch_set_options", "hmat_batch_get_info", "hmat_batch_autotune",
+                 "hmat_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -241,6 +274,125 @@ class HMatrix:
     def close(self):
         if self.handle:
             hmat_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
+
+
+def _i64_array(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+def hmat_batch_create(handles, nrhs, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0,
+                      null_options=False) -> int:
+    """Create a batch over handle values (ints); returns the batch handle (an int)."""
+    lib = load_library()
+    hs = _ptr_array(handles)
+    ks = (ctypes.c_int32 * len(nrhs))(*[int(k) for k in nrhs])
+    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit))
+    out = ctypes.c_void_p()
+    _check(lib.hmat_batch_create(hs if len(handles) else None, len(handles), ks if len(nrhs) else None,
+                                 None if null_options else ctypes.byref(opts), ctypes.byref(out)))
+    return out.value
+
+
+def hmat_batch_matvec(b: int, alpha: float, x_ptrs, ldx, beta: float, y_ptrs, ldy, stream: int | None = None):
+    _check(load_library().hmat_batch_matvec(b, float(alpha), _ptr_array(x_ptrs), _i64_array(ldx), float(beta),
+                                            _ptr_array(y_ptrs), _i64_array(ldy), stream))
+
+
+def hmat_batch_sync(b: int, stream: int | None = None):
+    _check(load_library().hmat_batch_sync(b, stream))
+
+
+def hmat_batch_set_options(b: int, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0):
+    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit))
+    _check(load_library().hmat_batch_set_options(b, ctypes.byref(opts)))
+
+
+def hmat_batch_get_info(b: int) -> dict:
+    info = hmat_batch_info()
+    _check(load_library().hmat_batch_get_info(b, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def hmat_batch_autotune(b: int, alpha: float, x_ptrs, ldx, beta: float, y_ptrs, ldy, stream: int | None = None,
+                        cache_path: str | None = None, reps: int = 5) -> dict:
+    chosen = hmat_batch_options()
+    _check(load_library().hmat_batch_autotune(b, float(alpha), _ptr_array(x_ptrs), _i64_array(ldx), float(beta),
+                                              _ptr_array(y_ptrs), _i64_array(ldy), stream,
+                                              cache_path.encode() if cache_path else None, int(reps),
+                                              ctypes.byref(chosen)))
+    return chosen.as_dict()
+
+
+def hmat_batch_destroy(b: int | None):
+    _check(load_library().hmat_batch_destroy(b))
+
+
+class HBatch:
+    """Owner of one batch over HMatrix members; operands are lists of torch CUDA tensors."""
+
+    def __init__(self, members, nrhs, *, use_graph=True, wg_per_cu=0, order=0, spin_limit=0):
+        self.members = list(members)   # kept alive: the batch references their device data
+        self.nrhs = [int(k) for k in nrhs]
+        self.handle = hmat_batch_create([m.handle for m in self.members], self.nrhs, use_graph=int(use_graph),
+                                        wg_per_cu=wg_per_cu, order=order, spin_limit=spin_limit)
+
+    def _operands(self, xs, ys):
+        import torch
+
+        if len(xs) != len(self.members) or len(ys) != len(self.members):
+            raise ValueError("one x and one y per member")
+        for t in list(xs) + list(ys):
+            if not t.is_cuda or t.dtype != torch.float32:
+                raise ValueError("operands must be float32 CUDA tensors")
+        ldx = [m._ld(x) for m, x in zip(self.members, xs)]
+        ldy = [m._ld(y) for m, y in zip(self.members, ys)]
+        return [x.data_ptr() for x in xs], ldx, [y.data_ptr() for y in ys], ldy
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+    def matvec(self, xs, ys, *, alpha=1.0, beta=0.0, stream=None):
+        xp, ldx, yp, ldy = self._operands(xs, ys)
+        hmat_batch_matvec(self.handle, alpha, xp, ldx, beta, yp, ldy, self._stream(stream))
+        return ys
+
+    def sync(self, stream=None):
+        hmat_batch_sync(self.handle, self._stream(stream))
+
+    def set_options(self, **kw):
+        hmat_batch_set_options(self.handle, **kw)
+
+    def info(self):
+        return hmat_batch_get_info(self.handle)
+
+    def autotune(self, xs, ys, *, alpha=1.0, beta=0.0, cache_path=None, reps=5, stream=None):
+        xp, ldx, yp, ldy = self._operands(xs, ys)
+        return hmat_batch_autotune(self.handle, alpha, xp, ldx, beta, yp, ldy, self._stream(stream),
+                                   cache_path=cache_path, reps=reps)
+
+    def close(self):
+        if self.handle:
+            hmat_batch_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

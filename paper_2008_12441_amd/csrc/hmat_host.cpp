@@ -2,6 +2,7 @@
 // device layout, host-side quantisation, device memory, kernel launches and
 // timing. The C ABI is declared in include/hmat.h.
 #include "hmat.h"
+#include "hmat_handle.h"
 #include "hmat_internal.h"
 
 #include <hip/hip_runtime_api.h>
@@ -26,23 +27,6 @@ using hmat::ZItem;
 using hmat::ZItem2;
 using hmat::ZSeg;
 
-struct hmat_handle {
-    int32_t device = 0;
-    int32_t storage = 0;
-    int32_t max_nrhs = 1;
-    hmat_info info{};
-    bool mr = false;               // multi-RHS (MFMA) layout
-    DevPlan plan{};
-    hmat::DevPlanMR mrp{};
-    std::vector<void *> dev_allocs;
-    // phase timing
-    bool timing = false;
-    std::vector<hipEvent_t> events;   // HMAT_NUM_PHASES + 1 per timed column
-    size_t events_used = 0;
-    double ms[HMAT_NUM_PHASES] = {0, 0, 0};
-    int64_t timed_calls = 0;
-};
-
 namespace {
 
 thread_local std::string t_err;
@@ -58,6 +42,19 @@ bool is_live(const hmat_handle *h) {
     std::lock_guard<std::mutex> lk(g_mu);
     return g_live.count(h) != 0;
 }
+
+}  // namespace
+
+hmat_status hmat::set_error(hmat_status s, const std::string &msg) { return fail(s, msg); }
+
+bool hmat::handle_live(const hmat_handle *h, int add_ref) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_live.count(h)) return false;
+    const_cast<hmat_handle *>(h)->batch_refs += add_ref;
+    return true;
+}
+
+namespace {
 
 template <class F>
 void parallel_for(int64_t n, F f) {
@@ -847,6 +844,8 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                 e.bofs = (base + (int64_t)kb * hp.ntmax) * bbytes;
                 e.srow = sg.kind == 0 ? sg.sidx : (int32_t)hp.zitems.size() + sg.sidx;
                 e.sleaf = sg.kind == 0 ? -1 : sg.leaf;
+                e.lseg = si - m.seg_base;
+                e.pad_ = 0;
                 hp.ustep.push_back(e);
             }
         }
@@ -1116,6 +1115,34 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     h->device = opts->device;
     h->storage = opts->storage;
     h->max_nrhs = opts->max_nrhs;
+    h->flags = opts->flags;
+    for (int64_t b = 0; b < nb; ++b) h->max_rank = std::max(h->max_rank, blocks[b].rank);
+    {
+        const float esz = opts->storage == HMAT_STORE_FP32 ? 4.0f : 2.0f;
+        if (h->mr) {
+            for (const hmat::MRChunk &c : hpm.chunks) {
+                h->chunk_rows.push_back(c.rows);
+                h->max_nseg = std::max(h->max_nseg, c.nseg);
+            }
+            for (const hmat::MRVUnit &u : hpm.vunits) {
+                int64_t steps = 0;
+                for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) steps += hpm.chunks[c].nkb;
+                h->cost_src.push_back((float)(steps * u.nm * 1024));
+            }
+            for (const hmat::MRTile &tl : hpm.tiles)
+                h->cost_tgt.push_back((float)((int64_t)hpm.chunks[tl.chunk].nsteps * tl.nm * 1024));
+        } else {
+            for (const ChunkMeta &c : hp.chunks) {
+                h->chunk_rows.push_back(c.rows);
+                const int64_t ntile = (c.rows + hmat::kWave - 1) / hmat::kWave;
+                h->cost_tgt.push_back((float)ntile * c.nq * hmat::kWave * hp.vw * esz);
+            }
+            for (const VTile &vt : hp.vtiles) {
+                const int64_t nvec = (hp.chunks[vt.chunk].rows + hp.vw - 1) / hp.vw;
+                h->cost_src.push_back((float)nvec * hmat::kWave * hp.vw * esz);
+            }
+        }
+    }
     hmat_info &in = h->info;
     in.n = t.n;
     in.leaf_depth = t.L;
@@ -1234,7 +1261,9 @@ hmat_status hmat_destroy(hmat_t h) {
     if (!h) return HMAT_OK;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        if (!g_live.erase(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown or already destroyed handle");
+        if (!g_live.count(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown or already destroyed handle");
+        if (h->batch_refs > 0) return fail(HMAT_ERR_INVALID_ARG, "handle is still used by a batch");
+        g_live.erase(h);
     }
     if (!h->dev_allocs.empty()) (void)hipSetDevice(h->device);
     release(h);

@@ -30,6 +30,7 @@
 //    z_ts = V_ts^T x_s over its siblings s, times the block's scales.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace hmat {
@@ -199,6 +200,8 @@ struct MRStep {           // one K-block step of a chunk's target-side contracti
     int64_t bofs;         // byte offset of its B fragments from zpack (xpack follows zpack)
     int32_t srow;         // row of its n-tile scales in the scale array (z rows, then x rows)
     int32_t sleaf;        // source leaf (x steps: selects the dense-block scale), -1 for z steps
+    int32_t lseg;         // index of its segment among the chunk's segments
+    int32_t pad_;
 };
 
 struct DevPlanMR {
@@ -226,6 +229,63 @@ struct DevPlanMR {
     const float *scales;      // n-tile scales: sz rows (one per z item), then sx rows (one per chunk)
 };
 
+// ---------------------------------------------------------------------------
+// Batched persistent launch: many handles applied by one kernel whose
+// workgroups take items from a queue. An item is a piece of one member's
+// product (up to four waves' worth of one stage, or one workgroup's); the
+// queue holds the stages in bands (source side, reduction, target side), so an
+// item only ever depends on items earlier in the queue, which keeps the queue
+// free of deadlock whatever the number of resident workgroups.
+// ---------------------------------------------------------------------------
+enum BKind : int32_t {
+    BK_SV = 0,   // single vector: up to 4 vtiles (one per wave)
+    BK_SZ1 = 1,  // single vector: up to 4 stage-1 reduction items
+    BK_SZ2 = 2,  // single vector: up to 4 stage-2 reduction items
+    BK_SU = 3,   // single vector: one chunk (whole workgroup)
+    BK_MX = 4,   // multi-RHS: X of one chunk packed (whole workgroup)
+    BK_MV = 5,   // multi-RHS: up to 4 V units
+    BK_MZ = 6,   // multi-RHS: up to 4 z items
+    BK_MU = 7    // multi-RHS: up to 4 row tiles
+};
+
+struct BItem {
+    int32_t member;
+    int32_t kind;         // BKind
+    int32_t first;        // first work index of the item's stage
+    int32_t count;        // work indices (waves) in the item, 1..4
+    int32_t dep;          // counter that must reach `need` before the item starts, -1 for none
+    int32_t need;
+    int32_t done;         // counter incremented when the item has completed, -1 for none
+    int32_t pad_;
+};
+
+struct BMember {
+    DevPlan sp;           // single-vector plan (mr == 0)
+    DevPlanMR mp;         // multi-RHS plan (mr == 1)
+    int32_t mr;
+    int32_t k;            // right-hand sides of this member
+};
+
+struct BArgs {            // per member, per call
+    const float *x;
+    float *y;
+    int64_t ldx;
+    int64_t ldy;
+    float alpha;
+    float beta;
+};
+
+struct BatchArgs {
+    const BMember *members;
+    const BArgs *args;
+    const BItem *items;
+    int32_t *ctl;         // [0] queue head, [1] error flag, [2..] stage counters
+    int32_t num_items;
+    int32_t num_ctl;
+    int32_t spin_limit;   // polls of a dependency wait before it flags an error and goes on
+    int32_t zs_rank;      // rows of the per-wave z scratch (multi-RHS members' largest rank)
+};
+
 // Kernel launchers (hmat_kernels.hip). Each returns a hipError_t as int.
 int launch_vphase(const DevPlan &p, const float *x, void *stream);
 int launch_zfinish(const DevPlan &p, void *stream);
@@ -234,5 +294,11 @@ int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float
 int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
 int launch_mr(const DevPlanMR &p, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
               float *y, int64_t ldy, void *stream, void (*mark)(void *ctx, int phase), void *ctx);
+// hmat_batch.hip: clear the counters, then run the persistent kernel with
+// `grid` workgroups and `lds` bytes of dynamic LDS.
+int launch_batch(const BatchArgs &a, int32_t storage, bool has_single, bool has_multi, int grid, size_t lds,
+                 void *stream);
+// The persistent kernel's occupancy (workgroups per CU) for that LDS size.
+int batch_max_wg_per_cu(int32_t storage, bool has_single, bool has_multi, size_t lds);
 
 }  // namespace hmat

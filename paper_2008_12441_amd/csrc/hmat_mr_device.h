@@ -1,0 +1,475 @@
+// Device bodies of the multi-RHS product on MFMA, shared by the per-handle
+// kernels and the batched persistent kernel.
+//
+// With k right-hand sides the local products of Sec. 4.1 become dense
+// contractions: the source side Z = V^T X (Eq. (4.2) for k columns) and the
+// target side Y += U Z and Y += D X (Eqs. (4.6)-(4.8)):
+//   mr_xpack   X -> B fragments per chunk (FP16: hi + lo halves, one
+//              power-of-two scale per chunk and n-tile of 16 columns);
+//   mr_vunit   per unit (level, source box, 64 V columns, up to 4 chunks):
+//              partial sums of V^T X, accumulated across the unit's chunks;
+//   mr_zitem   per low-rank block and n-tile: the fixed-order sum of its
+//              partials (Steps 2-4 collapsed), times the block's scales, packed
+//              as B fragments (FP16: with a power-of-two scale per n-tile);
+//   mr_tile    per row tile of one target leaf: Y over the z of every ancestor
+//              block and over x of every source leaf, written once.
+// Segment scales are powers of two, so moving the accumulators from one
+// segment's scale to the next is exact.
+#pragma once
+
+#include "hmat_device_common.h"
+
+namespace hmat {
+namespace dev {
+
+constexpr int kMaxRankMR = 128;
+
+// waves per SIMD the MFMA kernels are compiled for: two while the
+// accumulators and the double-buffered fragments fit in 256 registers
+template <int NT>
+struct Occupancy {
+    static constexpr int waves = NT <= 4 ? 2 : 1;
+};
+
+template <int STORE>
+struct MR;
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+// A buffer resource starting at p (raw, byte offsets below 4 GiB).
+__device__ inline rsrc_t make_rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, -1, 0x00020000);
+}
+
+constexpr int kNontemporal = 2;  // cache-policy bits of a streaming (read-once) load
+
+// Uniform (wave-wide) values read through the scalar cache.
+typedef __attribute__((address_space(4))) const float cfloat;
+__device__ inline float sload(const float *p, int i) { return ((cfloat *)p)[i]; }
+
+template <int AUX>
+__device__ inline f32x4 buf16(rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+}
+
+template <>
+struct MR<HMAT_STORE_FP32> {
+    static constexpr int KB = 16;     // inner indices per fragment
+    static constexpr int VW = 4;      // per lane
+    static constexpr int BFRAG = 64;  // 16-byte lane slots per B fragment
+    static constexpr bool SCALED = false;
+    using A = f32x4;
+    struct B {
+        f32x4 v;
+    };
+    // A fragment at byte offset soff of r; lane l reads bytes [16 l, 16 l + 16)
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) { return buf16<kNontemporal>(r, lane * 16, soff); }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
+        B b;
+        b.v = buf16<0>(r, lane * 16, soff);
+        return b;
+    }
+    __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
+        f32x4 t = {v[0], v[1], v[2], v[3]};
+        static_cast<f32x4 *>(base)[frag * BFRAG + lane] = t;
+    }
+    __device__ static inline void mma(const A &a, const B &b, f32x4 &c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.v[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.v[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.v[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b.v[3], c, 0, 0, 0);
+    }
+};
+
+template <>
+struct MR<HMAT_STORE_FP16_SCALED> {
+    static constexpr int KB = 32;
+    static constexpr int VW = 8;
+    static constexpr int BFRAG = 128;  // hi (64 slots) then lo (64 slots)
+    static constexpr bool SCALED = true;
+    using A = f16x8;
+    struct B {
+        f16x8 hi, lo;
+    };
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) {
+        return __builtin_bit_cast(f16x8, buf16<kNontemporal>(r, lane * 16, soff));
+    }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
+        B b;
+        b.hi = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16, soff));
+        b.lo = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16 + 1024, soff));
+        return b;
+    }
+    // v is already divided by the column scale: split into two halves whose
+    // sum carries about 22 significant bits
+    __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
+        f16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            hi[e] = (_Float16)v[e];
+            lo[e] = (_Float16)(v[e] - (float)hi[e]);
+        }
+        f16x8 *p = static_cast<f16x8 *>(base) + frag * BFRAG + lane;
+        p[0] = hi;
+        p[64] = lo;
+    }
+    __device__ static inline void mma(const A &a, const B &b, f32x4 &c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b.lo, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct MR<HMAT_STORE_BF16> {
+    static constexpr int KB = 32;
+    static constexpr int VW = 8;
+    static constexpr int BFRAG = 128;   // hi (64 slots) then lo (64 slots)
+    static constexpr bool SCALED = false;  // BF16 keeps FP32's exponent range
+    using A = bf16x8;
+    struct B {
+        bf16x8 hi, lo;
+    };
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) {
+        return __builtin_bit_cast(bf16x8, buf16<kNontemporal>(r, lane * 16, soff));
+    }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
+        B b;
+        b.hi = __builtin_bit_cast(bf16x8, buf16<0>(r, lane * 16, soff));
+        b.lo = __builtin_bit_cast(bf16x8, buf16<0>(r, lane * 16 + 1024, soff));
+        return b;
+    }
+    // two BF16 parts whose sum carries about 16 significant bits
+    __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            hi[e] = (__bf16)v[e];
+            lo[e] = (__bf16)(v[e] - (float)hi[e]);
+        }
+        bf16x8 *p = static_cast<bf16x8 *>(base) + frag * BFRAG + lane;
+        p[0] = hi;
+        p[64] = lo;
+    }
+    __device__ static inline void mma(const A &a, const B &b, f32x4 &c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, c, 0, 0, 0);
+    }
+};
+
+// power of two with |v| / s <= 2^14 for |v| <= amax (1 for amax == 0)
+__device__ inline float col_scale(float amax) {
+    if (!(amax > 0.0f)) return 1.0f;
+    int e = 0;
+    const float m = frexpf(amax, &e);
+    const int c = (m == 0.5f) ? e - 1 : e;
+    return ldexpf(1.0f, c - 14);
+}
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = fmaxf(v, __shfl_xor(v, s));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// The K-block step loop shared by both contractions. Step s multiplies the A
+// fragments af0 + s * nm + m (m < nm) with the B fragments that info(s)
+// points at (n-tile t at + t * 16 * BFRAG bytes). In the scaled form the B
+// values of step s carry the n-tile scales info(s).srow[t] * info(s).fac;
+// whenever those change, the accumulators are moved to the new scales
+// (powers of two, so the move is exact). info is called in increasing s.
+//
+// Scales are read through the scalar cache from info(s).srow, which requires
+// them to stay unchanged during the launch. With LANE_SCALES (one n-tile) the
+// caller instead loads the scales the wave needs into sv, one per lane, after
+// they were written, and step s takes lane info(s).sidx of it.
+// ---------------------------------------------------------------------------
+struct StepInfo {
+    int64_t bofs;        // byte offset of the step's B fragments
+    const float *srow;   // n-tile scales of the step's B (scaled form), read through the scalar cache
+    float fac;           // extra power-of-two factor of those scales
+    int32_t sidx;        // LANE_SCALES: lane of sv holding the step's scale (srow unused)
+};
+
+template <int STORE, int NT, bool LANE_SCALES, class Info>
+__device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int nm, int nsteps, int lane, Info info,
+                                  f32x4 (&acc)[4][NT], float (&scur)[NT], float sv) {
+    using F = MR<STORE>;
+    static_assert(!LANE_SCALES || NT == 1, "lane scales hold one n-tile");
+    auto scale_of = [&](const StepInfo &i, int t) {
+        return LANE_SCALES ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv), i.sidx))
+                           : sload(i.srow, t);
+    };
+    if (nsteps <= 0) return;
+    const rsrc_t ra = make_rsrc(static_cast<const char *>(A) + af0 * 1024);
+    // Four register sets for A (loaded four steps ahead), two for B (one step
+    // ahead). Every load is issued unconditionally, with indices clamped to
+    // the last step and m-subtile (re-reading fragments already in cache):
+    // loads under branches make the wait counters conservative and would
+    // drain the prefetched fragments at every step.
+    typename F::A a0[4], a1[4], a2[4], a3[4];
+    typename F::B b0[NT], b1[NT];
+    auto load_a = [&](typename F::A(&a)[4], int st) {
+        const int sc = st < nsteps ? st : nsteps - 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
+    };
+    auto load_b = [&](typename F::B(&b)[NT], int64_t bofs) {
+        const rsrc_t rb = make_rsrc(static_cast<const char *>(B) + bofs);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = F::loadB(rb, t * 16 * F::BFRAG, lane);
+    };
+    // scales of the current step's B and whether they differ from the last
+    // step's; the next step's are read one step ahead (scalar loads)
+    StepInfo ic = info(0), in_;
+    float sc[NT], sn[NT];
+    bool chg_c = true, chg_n = false;
+    if (F::SCALED) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sc[t] = scale_of(ic, t) * ic.fac;
+    }
+    auto step = [&](typename F::A(&a)[4], typename F::B(&b)[NT], typename F::B(&bn)[NT], int st) {
+        in_ = info(st + 1 < nsteps ? st + 1 : nsteps - 1);
+        load_b(bn, in_.bofs);
+        if (F::SCALED) {
+            chg_n = in_.srow != ic.srow || in_.sidx != ic.sidx || in_.fac != ic.fac;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sn[t] = chg_n ? scale_of(in_, t) * in_.fac : sc[t];
+            if (chg_c) {  // this step's B carries new n-tile scales: move the accumulators
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const float f = scur[t] * __builtin_amdgcn_rcpf(sc[t]);  // powers of two: exact
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) acc[m][t] *= f;
+                    scur[t] = sc[t];
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (m < nm)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) F::mma(a[m], b[t], acc[m][t]);
+        load_a(a, st + 4);
+        ic = in_;
+        if (F::SCALED) {
+            chg_c = chg_n;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sc[t] = sn[t];
+        }
+    };
+    load_b(b0, ic.bofs);
+    load_a(a0, 0);
+    load_a(a1, 1);
+    load_a(a2, 2);
+    load_a(a3, 3);
+    for (int st = 0; st < nsteps; st += 4) {
+        step(a0, b0, b1, st);
+        if (st + 1 >= nsteps) break;
+        step(a1, b1, b0, st + 1);
+        if (st + 2 >= nsteps) break;
+        step(a2, b0, b1, st + 2);
+        if (st + 3 >= nsteps) break;
+        step(a3, b1, b0, st + 3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// X -> B fragments for one (chunk, n-tile of 16 columns), by a workgroup of
+// 256 threads; red (16 x 17 floats) and sig (1 float) are LDS scratch.
+// ---------------------------------------------------------------------------
+template <int STORE>
+__device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx, int k,
+                                float (*red)[17], float *sig) {
+    using F = MR<STORE>;
+    constexpr int VW = F::VW;
+    constexpr int KB = F::KB;
+    const MRChunk ch = cload(p.chunks, c);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (F::SCALED) {
+        // 16 threads per column read 16 consecutive rows at a time
+        const int cc = tid >> 4, r0 = tid & 15;
+        const int n = nt * 16 + cc;
+        float m = 0.0f;
+        if (n < k) {
+            const float *col = x + (int64_t)n * ldx + ch.row_begin;
+            for (int i = r0; i < ch.rows; i += 16) m = fmaxf(m, fabsf(col[i]));
+        }
+        red[cc][r0] = m;
+        __syncthreads();
+        if (tid == 0) {
+            float a = 0.0f;
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j) a = fmaxf(a, red[i][j]);
+            const float s = col_scale(a);
+            sig[0] = s;
+            p.sx[(int64_t)c * p.ntmax + nt] = s;
+        }
+        __syncthreads();
+    }
+    const int n = nt * 16 + (lane & 15);
+    const float inv = F::SCALED ? 1.0f / sig[0] : 1.0f;
+    const float *col = x + (int64_t)n * ldx;
+    for (int kb = wave; kb < ch.nkb; kb += 4) {
+        // the leaf holding this K-block (leaves start on K-block boundaries)
+        int lf = 0;
+        while (lf + 1 < ch.nleaf && cload(p.leaves, ch.leaf_base + lf + 1).kb0 <= kb) ++lf;
+        const MRLeaf L = cload(p.leaves, ch.leaf_base + lf);
+        const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
+        float v[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int o = off0 + e;
+            v[e] = (n < k && o < L.rows) ? col[L.row_begin + o] * inv : 0.0f;
+        }
+        F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Source side, one wave per unit; acc[m-subtile][n-tile] are 16x16 tiles.
+// ---------------------------------------------------------------------------
+template <int STORE, int NT, bool LANE_SCALES>
+__device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
+    using F = MR<STORE>;
+    const MRVUnit u = cload(p.vunits, w);
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
+    float scur[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) scur[t] = 1.0f;
+    const int ncol = p.ntmax * 16;
+    // The unit's A fragments are [step][m-subtile] and its chunks' X
+    // fragments [step][n-tile], both contiguous over the unit's steps.
+    constexpr int64_t bbytes = 16 * F::BFRAG;
+    const int64_t b0 = cload(p.chunks, u.c0).xoff;
+    int nsteps = 0;
+    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
+    float sv = 1.0f;  // lane j: n-tile scale of the unit's chunk j
+    if (LANE_SCALES && F::SCALED && lane < u.nc) sv = p.sx[(int64_t)(u.c0 + lane) * p.ntmax];
+    int c = u.c0 - 1, cend = 0;  // chunk of the step asked for last, and the step where it ends
+    const int64_t ntm = p.ntmax;
+    auto info = [&](int st) {
+        while (st >= cend) {
+            ++c;
+            cend += cload(p.chunks, c).nkb;
+        }
+        return StepInfo{(b0 + (int64_t)st * ntm) * bbytes, LANE_SCALES ? nullptr : p.sx + (int64_t)c * ntm, 1.0f,
+                        LANE_SCALES ? c - u.c0 : 0};
+    };
+    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, acc, scur, sv);
+    float *out = p.part + u.poff;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[(int64_t)(16 * m + 4 * (lane >> 4) + i) * ncol + t * 16 + (lane & 15)] = acc[m][t][i] * scur[t];
+}
+
+// ---------------------------------------------------------------------------
+// Partial reduction and z packing, one wave per (low-rank block, n-tile); zs
+// is the wave's LDS scratch of kMaxRankMR x 16 floats.
+// ---------------------------------------------------------------------------
+template <int STORE>
+__device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, float (*zs)[16]) {
+    using F = MR<STORE>;
+    constexpr int VW = F::VW;
+    constexpr int KB = F::KB;
+    const MRZItem z = cload(p.zitems, item);
+    const int ncol = p.ntmax * 16;
+    const int nn = lane & 15, g = lane >> 4;
+    const int n = nt * 16 + nn;
+    const int64_t ustride = (int64_t)64 * ncol;
+    float amax = 0.0f;
+    for (int j = g; j < z.rank; j += 4) {
+        const int col = z.vcol + j;
+        const int64_t u0 = z.ubase + (int64_t)(col >> 6) * z.nu;
+        const float *src = p.part + u0 * ustride + (int64_t)(col & 63) * ncol + n;
+        float a0 = 0.0f, a1 = 0.0f;
+        int i = 0;
+        for (; i + 2 <= z.nu; i += 2) {
+            a0 += src[(int64_t)i * ustride];
+            a1 += src[(int64_t)(i + 1) * ustride];
+        }
+        if (i < z.nu) a0 += src[(int64_t)i * ustride];
+        const float s = (a0 + a1) * z.scale;
+        zs[j][nn] = s;
+        amax = fmaxf(amax, fabsf(s));
+    }
+    amax = wave_max(amax);
+    const float sig = F::SCALED ? col_scale(amax) : 1.0f;
+    if (F::SCALED && lane == 0) p.sz[(int64_t)item * p.ntmax + nt] = sig;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    const float inv = 1.0f / sig;
+    const int nkb = (z.rank + KB - 1) / KB;
+    for (int kb = 0; kb < nkb; ++kb) {
+        float v[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int j = kb * KB + VW * g + e;
+            v[e] = j < z.rank ? zs[j][nn] * inv : 0.0f;
+        }
+        F::storeB(p.zpack, z.zoff + (int64_t)kb * p.ntmax + nt, lane, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Target side, one wave per row tile (<= 64 rows of one target leaf): Y over
+// the z of every ancestor block and over x of every source leaf, written once.
+// ---------------------------------------------------------------------------
+template <int STORE, int NT, bool LANE_SCALES>
+__device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float alpha, float beta,
+                               float *__restrict__ y, int64_t ldy) {
+    using F = MR<STORE>;
+    const MRTile tl = cload(p.tiles, w);
+    const MRChunk ch = cload(p.chunks, tl.chunk);
+    const int nm = tl.nm;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
+    float scur[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) scur[t] = 1.0f;
+    // A fragments are contiguous over the tile's steps; the chunk's step
+    // table gives each step's B fragment (z of a block, or x of a source leaf).
+    const MRStep *steps = p.ustep + ch.step_base;
+    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nleaf;  // this target leaf's dense scales
+    float sv = 1.0f;  // lane j: n-tile scale of the chunk's segment j
+    if (LANE_SCALES && F::SCALED && lane < ch.nseg) {
+        const MRSeg sg = p.segs[ch.seg_base + lane];  // per lane: a vector load
+        sv = sg.kind == 0 ? p.sz[(int64_t)sg.sidx * p.ntmax] : p.sx[(int64_t)sg.sidx * p.ntmax];
+    }
+    auto info = [&](int st) {
+        const MRStep e = cload(steps, st);
+        return StepInfo{e.bofs, LANE_SCALES ? nullptr : p.scales + (int64_t)e.srow * p.ntmax,
+                        e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f, LANE_SCALES ? e.lseg : 0};
+    };
+    mfma_steps<STORE, NT, LANE_SCALES>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, acc, scur, sv);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = t * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * m + 4 * (lane >> 4) + i;
+                if (m < nm && row < tl.rows && n < k) {
+                    float *yp = y + (int64_t)(tl.row0 + row) + (int64_t)n * ldy;
+                    float v = alpha * (acc[m][t][i] * scur[t]);
+                    if (beta != 0.0f) v = fmaf(beta, *yp, v);
+                    *yp = v;
+                }
+            }
+        }
+}
+
+}  // namespace dev
+}  // namespace hmat

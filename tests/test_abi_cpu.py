@@ -220,3 +220,35 @@ def test_fp64_accum_lds_budget():
     assert st == 4 and "LDS" in msg, (st, msg)
     st, msg = _create_status(tree, blocks, flags=0)
     assert st != 4, msg
+
+
+def test_batch_entry_points_validate_before_device_calls():
+    lib = hm.load_library()
+    out = ctypes.c_void_p(77)
+    fake = (ctypes.c_void_p * 2)(0x1234, 0x5678)
+    ks = (ctypes.c_int32 * 2)(1, 1)
+    opts = hm.binding.hmat_batch_options(1, 0, 0, 0)
+    assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(opts), None) == 1
+    assert lib.hmat_batch_create(fake, 0, ks, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert out.value is None
+    assert lib.hmat_batch_create(None, 2, ks, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert lib.hmat_batch_create(fake, 2, None, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert "not a live handle" in hm.hmat_last_error()
+    for bad in [(2, 0, 0, 0), (1, -1, 0, 0), (1, 0, 2, 0), (1, 0, 0, -5), (1, 65, 0, 0)]:
+        o = hm.binding.hmat_batch_options(*bad)
+        assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(o), ctypes.byref(out)) == 1, bad
+    # NULL options take the defaults (the fake members are then rejected)
+    assert lib.hmat_batch_create(fake, 2, ks, None, ctypes.byref(out)) == 1
+    assert "not a live handle" in hm.hmat_last_error()
+    assert lib.hmat_batch_destroy(None) == 0
+    assert lib.hmat_batch_destroy(ctypes.c_void_p(0x1234)) == 1
+    nb = ctypes.c_void_p(0x1234)
+    p = (ctypes.c_void_p * 1)(0)
+    ld = (ctypes.c_int64 * 1)(1)
+    assert lib.hmat_batch_matvec(nb, 1.0, p, ld, 0.0, p, ld, None) == 1
+    assert lib.hmat_batch_sync(nb, None) == 1
+    assert lib.hmat_batch_set_options(nb, ctypes.byref(opts)) == 1
+    info = hm.binding.hmat_batch_info()
+    assert lib.hmat_batch_get_info(nb, ctypes.byref(info)) == 1
+    assert lib.hmat_batch_autotune(nb, 1.0, p, ld, 0.0, p, ld, None, None, 1, None) == 1
