@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-c3", action="store_true", help="skip the multi-RHS (3D, 64 RHS) leg")
     ap.add_argument("--c3-steps", type=int, default=20)
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched (256 matrices) leg")
+    ap.add_argument("--c4-steps", type=int, default=20)
+    ap.add_argument("--c4-members", type=int, default=256)
+    ap.add_argument("--c4-method", default="random", help="factor fill of the batched members")
     return ap.parse_args()
 
 
@@ -115,6 +119,117 @@ def traffic_from_profile(kernel_key):
     if prof.get("kernel") != kernel_key or prof.get("kernel_source_sha256_16") != digest:
         return None
     return int(prof["traffic_bytes_per_launch"])
+
+
+def time_fn(fn, steps, warmup, stream):
+    """Average ms of fn() over `steps` calls on `stream` (events around the loop)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def run_batched(stream, steps, warmup, count=256, method="random", with_oracle=True):
+    """Batched workload: `count` independent H-matrices on random sub-grids (2D log
+    kernel for even members, 3D 1/r kernel for odd ones, N log-uniform in [4096,
+    65536], ranks uniform on {8, 16, 32}), each applied to k = 1 and then k = 16
+    right-hand sides. One persistent launch over FP16 members (per-block scales)
+    against a loop of per-matrix FP32 products, with the batched FP32 and the
+    FP16 loop beside them."""
+    import ctypes
+
+    import torch
+
+    import paper_2008_12441_amd as hm
+    from hmat_inputs import batch_problems, build_batch_member, make_rhs
+
+    specs = batch_problems(count, seed=4)
+    t0 = time.time()
+    datas = []
+    for i, sp in enumerate(specs):
+        datas.append(build_batch_member(sp, method=method, seed=4000 + i, device="cuda"))
+        if (i + 1) % 64 == 0:
+            log(f"c4 members built: {i + 1}/{count} ({time.time() - t0:.1f} s)")
+    descs = []
+    for d in datas:
+        t = d.tree
+        descs.append(hm.make_descriptors(t.parent, t.begin, t.end, d.blocks.target, d.blocks.source,
+                                         d.blocks.rank, d.pool, d.off_a, d.off_b))
+    sum_n = int(sum(d.n for d in datas))
+    elems = int(sum(d.pool.size for d in datas))
+    out = {"workload": f"c4: {count} sub-grid H-matrices, 2D log / 3D 1/r kernels, N log-uniform in "
+                       f"[4096, 65536] (sum {sum_n}), leaf <= 64, ranks in {{8, 16, 32}}",
+           "members": count, "sum_n": sum_n, "stored_elements": elems, "factor_fill": method}
+    lib = hm.load_library()
+    cs = stream.cuda_stream
+    for k in (1, 16):
+        xs_np = [make_rhs(d.n, k, 5000 + i) for i, d in enumerate(datas)]
+        xs = [torch.from_numpy(np.ascontiguousarray(x.T)).cuda().T for x in xs_np]
+        ys = [torch.empty((k, d.n), device="cuda").T for d in datas]
+        vec_bytes = 8 * sum_n * k
+        res = {"nrhs": k}
+        ysave = {}
+        for form in ("fp32", "fp16"):
+            t1 = time.time()
+            hs = [hm.HMatrix(tr, bl, storage=form, max_nrhs=k) for tr, bl, _ in descs]
+            log(f"c4 k={k} {form}: 256 hmat_create in {time.time() - t1:.1f} s")
+            args = [(h.handle, k, ctypes.c_float(1.0), x.data_ptr(), d.n, ctypes.c_float(0.0), y.data_ptr(), d.n)
+                    for h, x, y, d in zip(hs, xs, ys, datas)]
+
+            def loop():
+                for a in args:
+                    if lib.hmat_matvec(*a, ctypes.c_void_p(cs)) != 0:
+                        raise hm.HmatError(6, hm.hmat_last_error())
+
+            loop_ms = time_fn(loop, steps, 2, stream)
+            b = hm.HBatch(hs, [k] * len(hs))
+            tuned = b.autotune(xs, ys, reps=5)
+            batch_ms = time_fn(lambda: b.matvec(xs, ys), steps, warmup, stream)
+            b.sync()
+            info = b.info()
+            ysave[form] = [y.cpu().numpy().astype(np.float64) for y in ys]
+            fbytes = int(sum(h.info["factor_bytes"] for h in hs))
+            res[form] = {"loop_ms": round(loop_ms, 4), "batched_ms": round(batch_ms, 4),
+                         "batched_GBps": round((fbytes + vec_bytes) / (batch_ms * 1e-3) / 1e9, 1),
+                         "alg_bytes": fbytes + vec_bytes, "tuned": tuned, "queue_items": info["num_items"],
+                         "grid": info["grid"]}
+            log(f"c4 k={k} {form}: loop {loop_ms:.3f} ms, batched {batch_ms:.3f} ms "
+                f"({res[form]['batched_GBps']} GB/s, tuned {tuned})")
+            b.close()
+            for h in hs:
+                h.close()
+            del hs, args
+            torch.cuda.empty_cache()
+        res["speedup_batched_fp16_vs_loop_fp32"] = round(res["fp32"]["loop_ms"] / res["fp16"]["batched_ms"], 3)
+        res["speedup_batched_fp16_vs_batched_fp32"] = round(res["fp32"]["batched_ms"] / res["fp16"]["batched_ms"], 3)
+        res["roofline_batched_fp16"] = {"bound": "hbm", "achieved": res["fp16"]["batched_GBps"],
+                                        "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                        "frac": round(res["fp16"]["batched_GBps"] / HBM_PEAK_GBPS, 4)}
+        if with_oracle:
+            import oracle
+
+            errs16, errs32 = [], []
+            for i in range(0, count, max(1, count // 16)):   # 16 sampled members
+                ref = oracle.oracle_matvec(datas[i], xs_np[i])
+                den = np.linalg.norm(ref, axis=0)
+                errs16.append(float((np.linalg.norm(ysave["fp16"][i] - ref, axis=0) / den).max()))
+                errs32.append(float((np.linalg.norm(ysave["fp32"][i] - ref, axis=0) / den).max()))
+            res["fp16_rel_err_vs_fp64_oracle_max"] = max(errs16)
+            res["fp32_rel_err_vs_fp64_oracle_max"] = max(errs32)
+            res["error_sample"] = "members 0, 16, 32, ...: max over members and columns of the relative 2-norm error"
+        out[f"k{k}"] = res
+        del xs, ys
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_multi_rhs(stream, steps, warmup, with_oracle=True):
@@ -309,6 +424,15 @@ def main():
         gc.collect()
         torch.cuda.empty_cache()
         result["multi_rhs_c3"] = run_multi_rhs(stream, args.c3_steps, 3, with_oracle=not args.no_cpu_baseline)
+    if not args.no_c4:
+        import gc
+
+        import torch
+
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["batched_c4"] = run_batched(stream, args.c4_steps, 3, count=args.c4_members, method=args.c4_method,
+                                           with_oracle=not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
 
 

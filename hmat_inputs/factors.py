@@ -198,6 +198,43 @@ def _put(pool, off, mat):
     pool[off:off + m * n] = np.asarray(mat, dtype=np.float64).T.reshape(-1).astype(np.float32)
 
 
+def _random_fill_torch(pool, blocks, off_a, off_b, sz, seed, device):
+    """The ``random`` fill drawn on a torch device: N(0,1) numbers times a
+    per-block factor (U: r^-1/2; V and D: |s|^-1/2), copied into ``pool``."""
+    import torch
+
+    starts, lens, scales = [], [], []
+    for b in range(len(blocks)):
+        t, s, r = int(blocks.target[b]), int(blocks.source[b]), int(blocks.rank[b])
+        m, n = int(sz[t]), int(sz[s])
+        if r == 0:
+            starts.append(int(off_a[b])); lens.append(m * n); scales.append(1.0 / math.sqrt(n))
+        else:
+            starts.append(int(off_a[b])); lens.append(m * r); scales.append(1.0 / math.sqrt(r))
+            starts.append(int(off_b[b])); lens.append(n * r); scales.append(1.0 / math.sqrt(n))
+    order = np.argsort(np.asarray(starts, np.int64), kind="stable")
+    starts = np.asarray(starts, np.int64)[order]
+    lens = np.asarray(lens, np.int64)[order]
+    scales = np.asarray(scales, np.float32)[order]
+    if len(starts) and (starts[0] != 0 or np.any(starts[1:] != starts[:-1] + lens[:-1])
+                        or starts[-1] + lens[-1] != pool.size):
+        raise AssertionError("factor pool is not tiled by the blocks")
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 0xD0)
+    chunk = 1 << 26
+    seg = np.concatenate([[0], np.cumsum(lens)])
+    i = 0
+    while i < len(lens):   # groups of whole blocks of at most `chunk` entries (or one larger block)
+        j = int(np.searchsorted(seg, seg[i] + chunk, side="right")) - 1
+        j = max(j, i + 1)
+        n_el = int(seg[j] - seg[i])
+        vals = torch.randn(n_el, generator=g, device=device, dtype=torch.float32)
+        fac = torch.repeat_interleave(torch.from_numpy(scales[i:j]).to(device),
+                                      torch.from_numpy(lens[i:j]).to(device))
+        pool[seg[i]:seg[j]] = (vals * fac).cpu().numpy()
+        i = j
+
+
 def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str = "svd",
                  seed: int = 0, oversample: int = 10, device=None, dedupe: bool = True,
                  gpu_min_entries: int = 1 << 24) -> HMatrixData:
@@ -212,7 +249,9 @@ def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str
                    an exact split, so the H-matrix equals the kernel matrix;
       ``random``   U, V, D filled with N(0,1) numbers scaled per block
                    (U by r^-1/2, V and D by |s|^-1/2), as in the paper's
-                   experiments, which use random fills.
+                   experiments, which use random fills. With ``device`` the
+                   normal numbers are drawn there by torch's generator (seeded
+                   from ``seed``), a different but equally seeded stream.
 
     For the kernel methods, blocks whose target and source boxes have the same
     shapes and the same relative offset hold the same entries (the kernels are
@@ -229,6 +268,9 @@ def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str
     pool = np.empty(total, dtype=np.float32)
     sz = tree.end - tree.begin
 
+    if method == "random" and device is not None:
+        _random_fill_torch(pool, blocks, off_a, off_b, sz, seed, device)
+        return HMatrixData(tree, blocks, pool, off_a, off_b, kind, method)
     if method == "random":
         rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xD0]))
         rng.standard_normal(size=total, dtype=np.float32, out=pool)

@@ -202,6 +202,8 @@ typedef struct hmat_batch_options {
     int32_t order;          /* queue order inside each stage band: 0 = largest item first,
                                1 = member by member (largest member first) */
     int32_t spin_limit;     /* polls before a dependency wait gives up and flags an error; 0 = 2^20 */
+    int32_t grain_kb;       /* an item groups consecutive work of one stage up to this many KiB of
+                               factor and operand traffic; 0 = 512 */
 } hmat_batch_options;
 
 typedef struct hmat_batch_info {
@@ -212,7 +214,7 @@ typedef struct hmat_batch_info {
     int32_t max_wg_per_cu;  /* most that can be resident */
     int32_t order;
     int32_t use_graph;
-    int32_t reserved;
+    int32_t grain_kb;
     int64_t lds_bytes;      /* dynamic LDS per workgroup */
     int64_t item_bytes;     /* factor bytes the items stream per call, layout padding included */
 } hmat_batch_info;
@@ -252,8 +254,9 @@ hmat_status hmat_batch_sync(hmat_batch_t b, void *stream);
 hmat_status hmat_batch_set_options(hmat_batch_t b, const hmat_batch_options *opts);
 hmat_status hmat_batch_get_info(hmat_batch_t b, hmat_batch_info *info);
 
-/* Autotuner: time every candidate (wg_per_cu in {1, 2, 3, 4, 6, 8} up to the
- * resident maximum, order in {0, 1}) on the given operands, `reps` timed
+/* Autotuner: time every candidate (wg_per_cu in {1, 2, 4, 8} up to the
+ * resident maximum, order in {0, 1}, grain_kb in {128, 512, 2048}) on the
+ * given operands, `reps` timed
  * calls each after two untimed ones, and keep the fastest. With a non-NULL
  * cache_path, a JSON file of earlier results keyed by a hash of the device and
  * the members' shapes is read first (a hit skips the timing) and updated

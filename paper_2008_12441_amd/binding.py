@@ -68,7 +68,7 @@ assert BLOCK_DTYPE.itemsize == ctypes.sizeof(hmat_block_desc)
 
 class hmat_batch_options(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("spin_limit", ctypes.c_int32)]
+                ("spin_limit", ctypes.c_int32), ("grain_kb", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -77,7 +77,7 @@ class hmat_batch_options(ctypes.Structure):
 class hmat_batch_info(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("num_items", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("max_wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+                ("use_graph", ctypes.c_int32), ("grain_kb", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
                 ("item_bytes", ctypes.c_int64)]
 
     def as_dict(self):
@@ -297,13 +297,13 @@ def _i64_array(vals):
     return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
 
 
-def hmat_batch_create(handles, nrhs, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0,
+def hmat_batch_create(handles, nrhs, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0, grain_kb=0,
                       null_options=False) -> int:
     """Create a batch over handle values (ints); returns the batch handle (an int)."""
     lib = load_library()
     hs = _ptr_array(handles)
     ks = (ctypes.c_int32 * len(nrhs))(*[int(k) for k in nrhs])
-    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit))
+    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit), int(grain_kb))
     out = ctypes.c_void_p()
     _check(lib.hmat_batch_create(hs if len(handles) else None, len(handles), ks if len(nrhs) else None,
                                  None if null_options else ctypes.byref(opts), ctypes.byref(out)))
@@ -319,8 +319,8 @@ def hmat_batch_sync(b: int, stream: int | None = None):
     _check(load_library().hmat_batch_sync(b, stream))
 
 
-def hmat_batch_set_options(b: int, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0):
-    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit))
+def hmat_batch_set_options(b: int, *, use_graph=1, wg_per_cu=0, order=0, spin_limit=0, grain_kb=0):
+    opts = hmat_batch_options(int(use_graph), int(wg_per_cu), int(order), int(spin_limit), int(grain_kb))
     _check(load_library().hmat_batch_set_options(b, ctypes.byref(opts)))
 
 
@@ -347,11 +347,12 @@ def hmat_batch_destroy(b: int | None):
 class HBatch:
     """Owner of one batch over HMatrix members; operands are lists of torch CUDA tensors."""
 
-    def __init__(self, members, nrhs, *, use_graph=True, wg_per_cu=0, order=0, spin_limit=0):
+    def __init__(self, members, nrhs, *, use_graph=True, wg_per_cu=0, order=0, spin_limit=0, grain_kb=0):
         self.members = list(members)   # kept alive: the batch references their device data
         self.nrhs = [int(k) for k in nrhs]
         self.handle = hmat_batch_create([m.handle for m in self.members], self.nrhs, use_graph=int(use_graph),
-                                        wg_per_cu=wg_per_cu, order=order, spin_limit=spin_limit)
+                                        wg_per_cu=wg_per_cu, order=order, spin_limit=spin_limit,
+                                        grain_kb=grain_kb)
 
     def _operands(self, xs, ys):
         import torch

@@ -11,12 +11,16 @@
 // raises the error flag and goes on, so a fault in the dependency bookkeeping
 // gives a reported error, never a hung GPU.
 //
-// Memory ordering: a producer item ends with an agent-scope release fence in
-// every thread, a workgroup barrier, then a release increment of the stage
-// counter by thread 0; a consumer's thread 0 polls the counter, and after a
-// barrier every thread takes an agent-scope acquire fence. On gfx950 these are
-// L2 write-back and invalidate operations, which reach across the XCDs, each of
-// which has its own L2.
+// Memory ordering: a producer item ends with every wave waiting for its own
+// stores to complete, a workgroup barrier, then an agent-scope release
+// increment of the stage counter by thread 0 (on gfx950 the release writes the
+// L2 back, reaching across the XCDs, each of which has its own L2); a consumer's
+// thread 0 polls the counter and takes an agent-scope acquire (L1/L2
+// invalidate) before the workgroup barrier that releases the other waves.
+//
+// An item is a run of consecutive work indices of one stage of one member,
+// grouped on the host up to a byte budget (the grain): waves take its indices
+// in turn, whole-workgroup stages take them one after the other.
 //
 // The multi-RHS bodies read the n-tile scales that earlier items of the same
 // launch wrote with vector loads into a register (one per lane) instead of
@@ -115,23 +119,28 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
         if (tid == 0) next = __hip_atomic_fetch_add(a.ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const BItem it = cload(a.items, t);
         if (it.dep >= 0) {
-            if (tid == 0) wait_counter(a.ctl, it.dep, it.need, a.spin_limit);
+            if (tid == 0) {
+                wait_counter(a.ctl, it.dep, it.need, a.spin_limit);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const BArgs ar = load_args(a.args + it.member);
         const int k = cload(a.members, it.member).k;
         if (HAS_S && it.kind <= BK_SU) {
             const DevPlan p = load_plan(&a.members[it.member].sp);
             if (it.kind == BK_SV) {
-                if (wave < it.count) sv_vtile<STORE, float>(p, it.first + wave, lane, ar.x);
+                for (int j = wave; j < it.count; j += 4) sv_vtile<STORE, float>(p, it.first + j, lane, ar.x);
             } else if (it.kind == BK_SZ1) {
-                if (wave < it.count) sv_z1<float>(p, it.first + wave, lane);
+                for (int j = wave; j < it.count; j += 4) sv_z1<float>(p, it.first + j, lane);
             } else if (it.kind == BK_SZ2) {
-                if (wave < it.count) sv_z2<float>(p, it.first + wave, lane);
+                for (int j = wave; j < it.count; j += 4) sv_z2<float>(p, it.first + j, lane);
             } else {
-                sv_chunk<STORE, float>(p, it.first, tid, reinterpret_cast<float *>(lds), ar.x, ar.y, ar.alpha,
-                                       ar.beta);
+                for (int j = 0; j < it.count; ++j) {
+                    if (j) __syncthreads();  // the previous chunk's operand is still being read from LDS
+                    sv_chunk<STORE, float>(p, it.first + j, tid, reinterpret_cast<float *>(lds), ar.x, ar.y,
+                                           ar.alpha, ar.beta);
+                }
             }
         }
         if (HAS_M && it.kind >= BK_MX) {
@@ -139,17 +148,21 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
             if (it.kind == BK_MX) {
                 float(*red)[17] = reinterpret_cast<float(*)[17]>(lds);
                 float *sig = reinterpret_cast<float *>(lds) + 16 * 17;
-                mr_xpack<STORE>(p, it.first, 0, ar.x, ar.ldx, k, red, sig);
+                for (int j = 0; j < it.count; ++j) {
+                    if (j) __syncthreads();  // red and sig are reused
+                    mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, red, sig);
+                }
             } else if (it.kind == BK_MV) {
-                if (wave < it.count) mr_vunit<STORE, 1, true>(p, it.first + wave, lane);
+                for (int j = wave; j < it.count; j += 4) mr_vunit<STORE, 1, true>(p, it.first + j, lane);
             } else if (it.kind == BK_MZ) {
                 float(*zs)[16] = reinterpret_cast<float(*)[16]>(lds) + wave * a.zs_rank;
-                if (wave < it.count) mr_zitem<STORE>(p, it.first + wave, 0, lane, zs);
+                for (int j = wave; j < it.count; j += 4) mr_zitem<STORE>(p, it.first + j, 0, lane, zs);
             } else {
-                if (wave < it.count) mr_tile<STORE, 1, true>(p, it.first + wave, lane, k, ar.alpha, ar.beta, ar.y, ar.ldy);
+                for (int j = wave; j < it.count; j += 4)
+                    mr_tile<STORE, 1, true>(p, it.first + j, lane, k, ar.alpha, ar.beta, ar.y, ar.ldy);
             }
         }
-        if (it.done >= 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (it.done >= 0) __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
         if (tid == 0) s_ticket[par] = next;
         __syncthreads();
         if (tid == 0 && it.done >= 0)

@@ -40,7 +40,7 @@ struct hmat_batch_handle {
     BArgs *d_args = nullptr;
     BItem *d_items = nullptr;
     int32_t *d_ctl = nullptr;
-    int32_t num_items = 0, num_ctl = 0, grid = 0;
+    int32_t num_items = 0, items_cap = 0, num_ctl = 0, grid = 0;
     BArgs *h_args = nullptr;        // pinned staging of the operand table
     std::vector<BArgs> cur_args;    // what d_args holds
     bool args_valid = false;
@@ -93,66 +93,62 @@ struct Costed {
     float cost;
 };
 
-// Every member's items; counters 2 + 3 i + {0, 1, 2} belong to member i.
-std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i) {
+// Every member's items; counters 2 + 3 i + {0, 1, 2} belong to member i. An
+// item is a run of consecutive work indices of one stage whose estimated
+// traffic reaches the grain (or the end of the stage).
+std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i, double grain) {
     std::vector<Costed> out;
     const hmat_handle *h = b->members[i];
     const int32_t c0 = 2 + 3 * i;
-    auto add = [&](int32_t kind, int32_t first, int32_t count, int32_t dep, int32_t need, int32_t done, float cost) {
-        BItem it{i, kind, first, count, dep, need, done, 0};
-        out.push_back(Costed{it, cost});
-    };
-    auto groups = [](int32_t n) { return (n + 3) / 4; };
-    auto sum = [](const std::vector<float> &v, int32_t f, int32_t n) {
-        float s = 0.0f;
-        for (int32_t j = f; j < f + n; ++j) s += v[j];
-        return s;
+    // items of one stage over work indices [0, n) with costs cost[]; returns how many
+    auto stage = [&](int32_t kind, int32_t n, const std::vector<float> &cost, int32_t dep, int32_t need,
+                     int32_t done) {
+        int32_t items = 0;
+        for (int32_t f = 0; f < n;) {
+            double c = 0.0;
+            int32_t e = f;
+            while (e < n && (e == f || c + cost[e] <= grain)) c += cost[e++];
+            out.push_back(Costed{BItem{i, kind, f, e - f, dep, need, done, 0}, (float)c});
+            ++items;
+            f = e;
+        }
+        return items;
     };
     if (!h->mr) {
         const hmat::DevPlan &p = h->plan;
-        const int32_t nsv = groups(p.num_vtiles), nz1 = groups(p.num_z1), nz2 = groups(p.num_z2);
-        for (int32_t f = 0; f < p.num_vtiles; f += 4) {
-            const int32_t n = std::min(4, p.num_vtiles - f);
-            add(hmat::BK_SV, f, n, -1, 0, c0, sum(h->cost_src, f, n));
-        }
-        for (int32_t f = 0; f < p.num_z1; f += 4)
-            add(hmat::BK_SZ1, f, std::min(4, p.num_z1 - f), nsv ? c0 : -1, nsv, c0 + 1, 4096.0f);
-        for (int32_t f = 0; f < p.num_z2; f += 4)
-            add(hmat::BK_SZ2, f, std::min(4, p.num_z2 - f), c0 + 1, nz1, c0 + 2, 4096.0f);
+        const int32_t nsv = stage(hmat::BK_SV, p.num_vtiles, h->cost_src, -1, 0, c0);
+        const int32_t nz1 = stage(hmat::BK_SZ1, p.num_z1, h->cost_z1, nsv ? c0 : -1, nsv, c0 + 1);
+        const int32_t nz2 = stage(hmat::BK_SZ2, p.num_z2, h->cost_z2, c0 + 1, nz1, c0 + 2);
         int32_t dep = -1, need = 0;
         if (nz2) dep = c0 + 2, need = nz2;
         else if (nz1) dep = c0 + 1, need = nz1;
         else if (nsv) dep = c0, need = nsv;
-        for (int32_t c = 0; c < p.num_chunks; ++c) add(hmat::BK_SU, c, 1, dep, need, -1, h->cost_tgt[c]);
+        stage(hmat::BK_SU, p.num_chunks, h->cost_tgt, dep, need, -1);
     } else {
         const hmat::DevPlanMR &p = h->mrp;
-        const int32_t nmx = p.num_chunks, nmv = groups(p.num_vunits), nmz = groups(p.num_zitems);
-        for (int32_t c = 0; c < p.num_chunks; ++c)
-            add(hmat::BK_MX, c, 1, -1, 0, c0, (float)h->chunk_rows[c] * 16 * 4 * 2);
-        for (int32_t f = 0; f < p.num_vunits; f += 4) {
-            const int32_t n = std::min(4, p.num_vunits - f);
-            add(hmat::BK_MV, f, n, c0, nmx, c0 + 1, sum(h->cost_src, f, n));
-        }
-        for (int32_t f = 0; f < p.num_zitems; f += 4)
-            add(hmat::BK_MZ, f, std::min(4, p.num_zitems - f), nmv ? c0 + 1 : c0, nmv ? nmv : nmx, c0 + 2, 4096.0f);
-        const int32_t dep = nmz ? c0 + 2 : c0, need = nmz ? nmz : nmx;
-        for (int32_t f = 0; f < p.num_tiles; f += 4) {
-            const int32_t n = std::min(4, p.num_tiles - f);
-            add(hmat::BK_MU, f, n, dep, need, -1, sum(h->cost_tgt, f, n));
-        }
+        std::vector<float> xcost(p.num_chunks);
+        for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2;
+        const int32_t nmx = stage(hmat::BK_MX, p.num_chunks, xcost, -1, 0, c0);
+        const int32_t nmv = stage(hmat::BK_MV, p.num_vunits, h->cost_src, c0, nmx, c0 + 1);
+        const int32_t nmz = stage(hmat::BK_MZ, p.num_zitems, h->cost_z1, nmv ? c0 + 1 : c0, nmv ? nmv : nmx, c0 + 2);
+        stage(hmat::BK_MU, p.num_tiles, h->cost_tgt, nmz ? c0 + 2 : c0, nmz ? nmz : nmx, -1);
     }
     return out;
 }
 
 // The queue: stage bands in order; inside a band, order 0 sorts items by cost
 // (largest first), order 1 keeps members together, largest member first.
-std::vector<BItem> build_queue(const hmat_batch_handle *b, int32_t order, int64_t *bytes) {
+constexpr int32_t kDefaultGrainKb = 512;
+
+std::vector<BItem> build_queue(const hmat_batch_handle *b, const hmat_batch_options &o, int64_t *bytes) {
+    const int32_t order = o.order;
+    const double grain = 1024.0 * (o.grain_kb > 0 ? o.grain_kb : kDefaultGrainKb);
     const int32_t n = (int32_t)b->members.size();
     std::vector<std::vector<Costed>> per(n);
     std::vector<double> total(n, 0.0);
     *bytes = 0;
     for (int32_t i = 0; i < n; ++i) {
-        per[i] = member_items(b, i);
+        per[i] = member_items(b, i, grain);
         for (const Costed &c : per[i]) total[i] += c.cost;
         for (const Costed &c : per[i])
             if (c.it.kind != hmat::BK_SZ1 && c.it.kind != hmat::BK_SZ2 && c.it.kind != hmat::BK_MZ &&
@@ -199,10 +195,18 @@ void drop_graph(hmat_batch_handle *b) {
 hmat_status configure(hmat_batch_handle *b) {
     drop_graph(b);
     int64_t bytes = 0;
-    const std::vector<BItem> q = build_queue(b, b->opts.order, &bytes);
+    const std::vector<BItem> q = build_queue(b, b->opts, &bytes);
     b->item_bytes = bytes;
-    if ((int32_t)q.size() != b->num_items) return set_error(HMAT_ERR_INVALID_ARG, "internal error: queue size");
-    hipError_t e = hipMemcpy(b->d_items, q.data(), q.size() * sizeof(BItem), hipMemcpyHostToDevice);
+    hipError_t e;
+    if ((int32_t)q.size() > b->items_cap) {  // the queue grows with a finer grain
+        if (b->d_items) (void)hipFree(b->d_items);
+        b->d_items = nullptr;
+        b->items_cap = 0;
+        if ((e = hipMalloc(&b->d_items, sizeof(BItem) * q.size())) != hipSuccess) return hip_fail("hipMalloc", e);
+        b->items_cap = (int32_t)q.size();
+    }
+    b->num_items = (int32_t)q.size();
+    e = hipMemcpy(b->d_items, q.data(), q.size() * sizeof(BItem), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail("hipMemcpy", e);
     const int32_t wg = b->opts.wg_per_cu > 0 ? std::min(b->opts.wg_per_cu, b->max_wg) : b->max_wg;
     b->grid = std::max(1, wg * b->cus);
@@ -243,6 +247,7 @@ hmat_status check_options(const hmat_batch_options *o) {
     if (o->wg_per_cu < 0 || o->wg_per_cu > 64) return set_error(HMAT_ERR_INVALID_ARG, "wg_per_cu out of [0, 64]");
     if (o->order != 0 && o->order != 1) return set_error(HMAT_ERR_INVALID_ARG, "order must be 0 or 1");
     if (o->spin_limit < 0) return set_error(HMAT_ERR_INVALID_ARG, "spin_limit must be >= 0");
+    if (o->grain_kb < 0 || o->grain_kb > (1 << 20)) return set_error(HMAT_ERR_INVALID_ARG, "grain_kb out of [0, 2^20]");
     return HMAT_OK;
 }
 
@@ -251,7 +256,7 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
     if (!hs || !nrhs) return set_error(HMAT_ERR_INVALID_ARG, "members and nrhs must not be NULL");
     if (count < 1) return set_error(HMAT_ERR_INVALID_ARG, "count must be >= 1");
     if (count > (1 << 20)) return set_error(HMAT_ERR_INVALID_ARG, "too many members");
-    b->opts = hmat_batch_options{1, 0, 0, 0};
+    b->opts = hmat_batch_options{1, 0, 0, 0, 0};
     if (opts) {
         hmat_status s = check_options(opts);
         if (s != HMAT_OK) return s;
@@ -313,13 +318,9 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
         mem[i].mr = b->members[i]->mr ? 1 : 0;
         mem[i].k = nrhs[i];
     }
-    int64_t bytes = 0;
-    b->num_items = (int32_t)build_queue(b, 0, &bytes).size();
     b->num_ctl = 2 + 3 * count;
     if ((e = hipMalloc(&b->d_members, sizeof(BMember) * count)) != hipSuccess) return hip_fail("hipMalloc", e);
     if ((e = hipMalloc(&b->d_args, sizeof(BArgs) * count)) != hipSuccess) return hip_fail("hipMalloc", e);
-    if ((e = hipMalloc(&b->d_items, sizeof(BItem) * std::max(1, b->num_items))) != hipSuccess)
-        return hip_fail("hipMalloc", e);
     if ((e = hipMalloc(&b->d_ctl, sizeof(int32_t) * b->num_ctl)) != hipSuccess) return hip_fail("hipMalloc", e);
     if ((e = hipHostMalloc((void **)&b->h_args, sizeof(BArgs) * count, hipHostMallocDefault)) != hipSuccess) {
         b->h_args = nullptr;
@@ -421,7 +422,7 @@ std::string batch_key(const hmat_batch_handle *b) {
 
 struct CacheEntry {
     std::string key;
-    int wg = 0, order = 0;
+    int wg = 0, order = 0, grain = 0;
     double ms = 0.0;
 };
 
@@ -446,10 +447,12 @@ std::vector<CacheEntry> load_cache(const char *path) {
             const size_t q = obj.find(name);
             return q != std::string::npos && std::sscanf(obj.c_str() + q + std::strlen(name), " : %lf", v) == 1;
         };
-        double wg = 0, order = 0, ms = 0;
-        if (num("\"wg_per_cu\"", &wg) && num("\"order\"", &order) && num("\"ms\"", &ms)) {
+        double wg = 0, order = 0, grain = 0, ms = 0;
+        if (num("\"wg_per_cu\"", &wg) && num("\"order\"", &order) && num("\"grain_kb\"", &grain) &&
+            num("\"ms\"", &ms)) {
             c.wg = (int)wg;
             c.order = (int)order;
+            c.grain = (int)grain;
             c.ms = ms;
             out.push_back(c);
         }
@@ -466,8 +469,10 @@ bool save_cache(const char *path, const std::vector<CacheEntry> &entries) {
         f << "{\n  \"format\": \"hmat-batch-tuning-1\",\n  \"entries\": [";
         for (size_t i = 0; i < entries.size(); ++i) {
             char line[256];
-            std::snprintf(line, sizeof(line), "%s\n    {\"key\": \"%s\", \"wg_per_cu\": %d, \"order\": %d, \"ms\": %.6f}",
-                          i ? "," : "", entries[i].key.c_str(), entries[i].wg, entries[i].order, entries[i].ms);
+            std::snprintf(line, sizeof(line),
+                          "%s\n    {\"key\": \"%s\", \"wg_per_cu\": %d, \"order\": %d, \"grain_kb\": %d, \"ms\": %.6f}",
+                          i ? "," : "", entries[i].key.c_str(), entries[i].wg, entries[i].order, entries[i].grain,
+                          entries[i].ms);
             f << line;
         }
         f << "\n  ]\n}\n";
@@ -564,6 +569,7 @@ hmat_status hmat_batch_get_info(hmat_batch_t b, hmat_batch_info *info) {
     r.max_wg_per_cu = b->max_wg;
     r.order = b->opts.order;
     r.use_graph = b->opts.use_graph;
+    r.grain_kb = b->opts.grain_kb > 0 ? b->opts.grain_kb : kDefaultGrainKb;
     r.lds_bytes = (int64_t)b->lds;
     r.item_bytes = b->item_bytes;
     *info = r;
@@ -585,9 +591,11 @@ hmat_status hmat_batch_autotune(hmat_batch_t b, float alpha, const float *const 
         hmat_batch_options best = b->opts;
         bool hit = false;
         for (const CacheEntry &c : cache)
-            if (c.key == key && c.wg >= 1 && c.wg <= b->max_wg && (c.order == 0 || c.order == 1)) {
+            if (c.key == key && c.wg >= 1 && c.wg <= b->max_wg && (c.order == 0 || c.order == 1) && c.grain >= 1 &&
+                c.grain <= (1 << 20)) {
                 best.wg_per_cu = c.wg;
                 best.order = c.order;
+                best.grain_kb = c.grain;
                 hit = true;
             }
         double best_ms = 0.0;
@@ -600,12 +608,13 @@ hmat_status hmat_batch_autotune(hmat_batch_t b, float alpha, const float *const 
                 return hip_fail("hipEventCreate", e);
             }
             double best_t = 1e300;
-            for (int wg : {1, 2, 3, 4, 6, 8}) {
+            for (int wg : {1, 2, 4, 8}) {
                 if (wg > b->max_wg) continue;
-                for (int order : {0, 1}) {
+                for (int cand = 0; cand < 6; ++cand) {
                     hmat_batch_options o = b->opts;
                     o.wg_per_cu = wg;
-                    o.order = order;
+                    o.order = cand & 1;
+                    o.grain_kb = cand < 2 ? 128 : cand < 4 ? 512 : 2048;
                     if ((s = hmat_batch_set_options(b, &o)) != HMAT_OK) break;
                     for (int w = 0; w < 2 && s == HMAT_OK; ++w) s = hmat_batch_matvec(b, alpha, x, ldx, beta, y, ldy, st);
                     if (s == HMAT_OK && (e = hipEventRecord(e0, st)) != hipSuccess) s = hip_fail("hipEventRecord", e);
@@ -632,7 +641,7 @@ hmat_status hmat_batch_autotune(hmat_batch_t b, float alpha, const float *const 
             std::vector<CacheEntry> keep;
             for (const CacheEntry &c : cache)
                 if (c.key != key) keep.push_back(c);
-            keep.push_back(CacheEntry{key, best.wg_per_cu, best.order, best_ms});
+            keep.push_back(CacheEntry{key, best.wg_per_cu, best.order, best.grain_kb, best_ms});
             if (!save_cache(cache_path, keep))
                 return set_error(HMAT_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache_path);
         }

@@ -23,6 +23,7 @@ struct hmat_handle {
     // work estimates for schedulers: bytes streamed per source-side work index
     // (vtile, or V unit) and per target-side work index (chunk, or row tile)
     std::vector<float> cost_src, cost_tgt;
+    std::vector<float> cost_z1, cost_z2;  // per reduction item (multi-RHS: z items in cost_z1)
     std::vector<int32_t> chunk_rows;  // rows of each chunk
     int32_t max_nseg = 0;             // multi-RHS: most target-side segments of a chunk
     int32_t max_rank = 0;             // largest rank of a low-rank block

@@ -1131,6 +1131,8 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
             }
             for (const hmat::MRTile &tl : hpm.tiles)
                 h->cost_tgt.push_back((float)((int64_t)hpm.chunks[tl.chunk].nsteps * tl.nm * 1024));
+            for (const hmat::MRZItem &z : hpm.zitems)  // partials read, B fragments written (one n-tile)
+                h->cost_z1.push_back((float)z.nu * z.rank * 64 + (float)z.rank * 64 * 2);
         } else {
             for (const ChunkMeta &c : hp.chunks) {
                 h->chunk_rows.push_back(c.rows);
@@ -1141,6 +1143,8 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 const int64_t nvec = (hp.chunks[vt.chunk].rows + hp.vw - 1) / hp.vw;
                 h->cost_src.push_back((float)nvec * hmat::kWave * hp.vw * esz);
             }
+            for (const ZItem &z : hp.z1) h->cost_z1.push_back((float)(z.nchunks + 1) * z.rank * 4);
+            for (const ZItem2 &z : hp.z2) h->cost_z2.push_back((float)(z.nslices + 1) * z.rank * 4);
         }
     }
     hmat_info &in = h->info;

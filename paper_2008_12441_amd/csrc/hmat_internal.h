@@ -238,21 +238,21 @@ struct DevPlanMR {
 // free of deadlock whatever the number of resident workgroups.
 // ---------------------------------------------------------------------------
 enum BKind : int32_t {
-    BK_SV = 0,   // single vector: up to 4 vtiles (one per wave)
-    BK_SZ1 = 1,  // single vector: up to 4 stage-1 reduction items
-    BK_SZ2 = 2,  // single vector: up to 4 stage-2 reduction items
-    BK_SU = 3,   // single vector: one chunk (whole workgroup)
-    BK_MX = 4,   // multi-RHS: X of one chunk packed (whole workgroup)
-    BK_MV = 5,   // multi-RHS: up to 4 V units
-    BK_MZ = 6,   // multi-RHS: up to 4 z items
-    BK_MU = 7    // multi-RHS: up to 4 row tiles
+    BK_SV = 0,   // single vector: vtiles (a wave each)
+    BK_SZ1 = 1,  // single vector: stage-1 reduction items (a wave each)
+    BK_SZ2 = 2,  // single vector: stage-2 reduction items (a wave each)
+    BK_SU = 3,   // single vector: chunks (the whole workgroup each)
+    BK_MX = 4,   // multi-RHS: X packing of chunks (the whole workgroup each)
+    BK_MV = 5,   // multi-RHS: V units (a wave each)
+    BK_MZ = 6,   // multi-RHS: z items (a wave each)
+    BK_MU = 7    // multi-RHS: row tiles (a wave each)
 };
 
 struct BItem {
     int32_t member;
     int32_t kind;         // BKind
     int32_t first;        // first work index of the item's stage
-    int32_t count;        // work indices (waves) in the item, 1..4
+    int32_t count;        // consecutive work indices in the item, >= 1
     int32_t dep;          // counter that must reach `need` before the item starts, -1 for none
     int32_t need;
     int32_t done;         // counter incremented when the item has completed, -1 for none

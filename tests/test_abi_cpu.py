@@ -227,7 +227,7 @@ def test_batch_entry_points_validate_before_device_calls():
     out = ctypes.c_void_p(77)
     fake = (ctypes.c_void_p * 2)(0x1234, 0x5678)
     ks = (ctypes.c_int32 * 2)(1, 1)
-    opts = hm.binding.hmat_batch_options(1, 0, 0, 0)
+    opts = hm.binding.hmat_batch_options(1, 0, 0, 0, 0)
     assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(opts), None) == 1
     assert lib.hmat_batch_create(fake, 0, ks, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert out.value is None
@@ -235,7 +235,8 @@ def test_batch_entry_points_validate_before_device_calls():
     assert lib.hmat_batch_create(fake, 2, None, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert "not a live handle" in hm.hmat_last_error()
-    for bad in [(2, 0, 0, 0), (1, -1, 0, 0), (1, 0, 2, 0), (1, 0, 0, -5), (1, 65, 0, 0)]:
+    for bad in [(2, 0, 0, 0, 0), (1, -1, 0, 0, 0), (1, 0, 2, 0, 0), (1, 0, 0, -5, 0), (1, 65, 0, 0, 0),
+                (1, 0, 0, 0, -1), (1, 0, 0, 0, (1 << 20) + 1)]:
         o = hm.binding.hmat_batch_options(*bad)
         assert lib.hmat_batch_create(fake, 2, ks, ctypes.byref(o), ctypes.byref(out)) == 1, bad
     # NULL options take the defaults (the fake members are then rejected)

@@ -142,9 +142,9 @@ def test_batch_mixed_members_alpha_beta_options_and_replays():
     y0 = [torch.from_numpy(np.ascontiguousarray(y.T)).cuda().T for y in y0n]
     ref_bits = _single_runs(handles, xs, ks, alpha=0.5, beta=-2.0, y0s=y0)
     with hm.HBatch(handles, ks) as b:
-        for opts in [dict(use_graph=1, wg_per_cu=0, order=0), dict(use_graph=0, wg_per_cu=1, order=0),
-                     dict(use_graph=1, wg_per_cu=1, order=1), dict(use_graph=0, wg_per_cu=2, order=1),
-                     dict(use_graph=1, wg_per_cu=3, order=0)]:
+        for opts in [dict(use_graph=1, wg_per_cu=0, order=0), dict(use_graph=0, wg_per_cu=1, order=0, grain_kb=1),
+                     dict(use_graph=1, wg_per_cu=1, order=1, grain_kb=64), dict(use_graph=0, wg_per_cu=2, order=1),
+                     dict(use_graph=1, wg_per_cu=3, order=0, grain_kb=1 << 16)]:
             b.set_options(**opts)
             for rep in range(3):
                 for y, yi in zip(ys, y0):
@@ -216,9 +216,11 @@ def test_batch_autotune_and_cache(tmp_path):
         chosen = b.autotune(xs, ys, cache_path=cache, reps=2)
         info = b.info()
         assert info["wg_per_cu"] == chosen["wg_per_cu"] and info["order"] == chosen["order"]
+        assert info["grain_kb"] == chosen["grain_kb"]
         doc = json.load(open(cache))
         assert doc["format"] == "hmat-batch-tuning-1" and len(doc["entries"]) == 1
         assert doc["entries"][0]["wg_per_cu"] == chosen["wg_per_cu"]
+        assert doc["entries"][0]["grain_kb"] == chosen["grain_kb"]
         again = b.autotune(xs, ys, cache_path=cache, reps=2)   # cache hit
         assert again == chosen
         b.matvec(xs, ys)
