@@ -39,13 +39,24 @@ typedef enum hmat_status {
 } hmat_status;
 
 /* How the factors are stored on the device. Quantisation happens on the host
- * inside hmat_create; the device only dequantises, exactly. Accumulation is
- * FP32 in every form. */
+ * inside hmat_create; the device only dequantises (exactly, up to the one
+ * FP16 rounding the FP8 forms state). Accumulation is FP32 in every form. */
 typedef enum hmat_storage {
     HMAT_STORE_FP32 = 0,          /* D, U, V in FP32 */
     HMAT_STORE_FP16_SCALED = 1,   /* D, U, V in FP16, one power-of-two scale per stored array
                                      D_ts, U_ts, V_ts: s = 2^(ceil(log2 amax) - 15), q = RNE(v / s) */
-    HMAT_STORE_BF16 = 2           /* D, U, V in BF16, q = RNE(v), no scales */
+    HMAT_STORE_BF16 = 2,          /* D, U, V in BF16, q = RNE(v), no scales */
+    HMAT_STORE_FP8 = 3,           /* U, V in FP8 E4M3 (OCP E4M3FN) as a hi + lo pair per element with
+                                     power-of-two scales per factor column j:
+                                       s_j = 2^ceil(log2(amax_j / 448)), hi = RNE_e4m3(v / s_j),
+                                       r = v / s_j - hi, s'_j = 2^ceil(log2(amax_j(r) / 448)),
+                                       lo = RNE_e4m3(r / s'_j)  (all-zero columns: scale 1);
+                                     the device multiplies with RNE_f16(hi + s'_j lo) (exact FP16
+                                     conversions, one FP16 rounding) and folds s_j into z.
+                                     D in BF16: q = RNE_bf16(v / s) with the per-block power of two s
+                                     of the FP16 form, held as FP16 on the device (exact for
+                                     |v / s| >= 2^-14). Multi-RHS handles (max_nrhs > 1) only. */
+    HMAT_STORE_FP8_F16D = 4       /* U, V as in HMAT_STORE_FP8; D as in HMAT_STORE_FP16_SCALED */
 } hmat_storage;
 
 /* Domain tree (Def. "Domain tree", Sec. 2). Node 0 is the root with
@@ -229,8 +240,8 @@ typedef struct hmat_batch_info {
  * member must not run hmat_matvec concurrently with the batch. opts may be
  * NULL (defaults: graph on, as many workgroups as fit, largest item first).
  *
- * Errors: INVALID_ARG; UNSUPPORTED (a multi-RHS member whose chunks have more
- * than 64 target-side segments); NOMEM; DEVICE. */
+ * Errors: INVALID_ARG; UNSUPPORTED (a member in an FP8 form, or a multi-RHS
+ * member whose chunks have more than 64 target-side segments); NOMEM; DEVICE. */
 hmat_status hmat_batch_create(const hmat_t *members, int32_t count, const int32_t *nrhs,
                               const hmat_batch_options *opts, hmat_batch_t *out);
 

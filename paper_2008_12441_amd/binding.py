@@ -25,7 +25,10 @@ HMAT_ERR_DEVICE = 6
 HMAT_STORE_FP32 = 0
 HMAT_STORE_FP16_SCALED = 1
 HMAT_STORE_BF16 = 2
-STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED, "bf16": HMAT_STORE_BF16}
+HMAT_STORE_FP8 = 3
+HMAT_STORE_FP8_F16D = 4
+STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED, "bf16": HMAT_STORE_BF16,
+           "fp8": HMAT_STORE_FP8, "fp8_f16d": HMAT_STORE_FP8_F16D}
 
 HMAT_FLAG_FP64_ACCUM = 1
 

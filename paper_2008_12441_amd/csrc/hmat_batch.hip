@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
                 for (int j = wave; j < it.count; j += 4) mr_zitem<STORE>(p, it.first + j, 0, lane, zs);
             } else {
                 for (int j = wave; j < it.count; j += 4)
-                    mr_tile<STORE, 1, true>(p, it.first + j, lane, k, ar.alpha, ar.beta, ar.y, ar.ldy);
+                    mr_tile<STORE, 1, true>(p, it.first + j, lane, k, ar.alpha, ar.beta, ar.y, ar.ldy, nullptr);
             }
         }
         if (it.done >= 0) __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2

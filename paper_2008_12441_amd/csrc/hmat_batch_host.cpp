@@ -274,6 +274,8 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
             return set_error(HMAT_ERR_INVALID_ARG, "members must share one device and one storage form");
         }
         if (h->flags != 0) return set_error(HMAT_ERR_INVALID_ARG, "members must be created without flags");
+        if (h->storage > HMAT_STORE_BF16)
+            return set_error(HMAT_ERR_UNSUPPORTED, "batches take FP32, FP16 and BF16 members");
         if (!h->mr) {
             if (nrhs[i] != 1)
                 return set_error(HMAT_ERR_INVALID_ARG, "member " + std::to_string(i) + ": single-vector handle takes nrhs 1");

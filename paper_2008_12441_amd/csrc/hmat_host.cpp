@@ -127,6 +127,73 @@ float pow2_scale_f16(float amax) {
     return std::ldexp(1.0f, std::max(c - 15, -126));
 }
 
+// FP8 E4M3 (OCP E4M3FN: bias 7, 3 mantissa bits, subnormals, largest finite
+// 448, no infinities) code of x by round-to-nearest-even; |x| <= 448.
+uint8_t e4m3_rne(double x) {
+    const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    const double a = std::fabs(x);
+    if (a == 0.0) return sign;
+    int e = 0;
+    std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1): the leading bit has weight 2^(e-1)
+    const int lead = std::max(e - 1, -6);                 // subnormals share the exponent of 2^-6
+    const double q = std::nearbyint(std::ldexp(a, 3 - lead));  // significand in units of 2^(lead-3), RNE
+    int32_t code;
+    if (lead == -6 && q < 8.0)
+        code = (int32_t)q;                                // subnormal (q = 8 is the smallest normal)
+    else if (q >= 16.0)
+        code = ((lead + 1 + 7) << 3);                     // rounded up to the next binade
+    else
+        code = ((lead + 7) << 3) | ((int32_t)q - 8);
+    return (uint8_t)(sign | code);
+}
+
+double e4m3_value(uint8_t c) {
+    const int ex = (c >> 3) & 0xF, m = c & 7;
+    const double v = ex == 0 ? std::ldexp((double)m, -9) : std::ldexp(8.0 + m, ex - 10);
+    return (c & 0x80) ? -v : v;
+}
+
+// Smallest power of two s with a / s <= 448 (1 for a == 0): the E4M3 column
+// scale 2^ceil(log2(a / 448)), chosen without rounding error.
+double pow2_scale_e4m3(double a) {
+    if (!(a > 0.0)) return 1.0;
+    int e = 0;
+    std::frexp(a / 448.0, &e);
+    int k = e;
+    while (a > std::ldexp(448.0, k)) ++k;
+    while (k > -1074 && a <= std::ldexp(448.0, k - 1)) --k;
+    return std::ldexp(1.0, k);
+}
+
+// FP16 code of a power of two (0 below the FP16 range).
+uint16_t f16_pow2_code(double s) {
+    return f32_to_f16_rne((float)s);
+}
+
+// Column scales of an FP8 factor (rows x cols, column-major, ld): per column
+// j, s[2 j] = s_j and s[2 j + 1] = s'_j.
+void e4m3_column_scales(const float *a, int64_t rows, int64_t cols, int64_t ld, float *s) {
+    for (int64_t j = 0; j < cols; ++j) {
+        double am = 0.0;
+        for (int64_t i = 0; i < rows; ++i) am = std::max(am, (double)std::fabs(a[i + j * ld]));
+        const double sj = pow2_scale_e4m3(am);
+        double ar = 0.0;
+        for (int64_t i = 0; i < rows; ++i) {
+            const double u = (double)a[i + j * ld] / sj;
+            ar = std::max(ar, std::fabs(u - e4m3_value(e4m3_rne(u))));
+        }
+        s[2 * j] = (float)sj;
+        s[2 * j + 1] = (float)pow2_scale_e4m3(ar);
+    }
+}
+
+// hi and lo codes of v in a column with scales (sj, slj).
+inline void e4m3_hilo(float v, float sj, float slj, uint8_t *hi, uint8_t *lo) {
+    const double u = (double)v / sj;
+    *hi = e4m3_rne(u);
+    *lo = e4m3_rne((u - e4m3_value(*hi)) / slj);
+}
+
 float col_major_amax(const float *a, int64_t rows, int64_t cols, int64_t ld, bool *finite) {
     float m = 0.0f;
     for (int64_t j = 0; j < cols; ++j)
@@ -634,6 +701,11 @@ constexpr int32_t kMaxRankMR = 128;
 struct HostPlanMR {
     int32_t kb = 16, vw = 4, ntmax = 1;
     bool bf16 = false;
+    bool fp8 = false;        // U, V as E4M3 hi + lo (HMAT_STORE_FP8, HMAT_STORE_FP8_F16D)
+    bool dense_bf16 = false; // D as BF16 of v / s_D (HMAT_STORE_FP8)
+    std::vector<std::vector<float>> colU, colV;  // FP8: per low-rank block, (s_j, s'_j) per column
+    std::vector<uint16_t> vlo, ulo;              // FP8: FP16 lo-scale tables
+    std::vector<float> zcol;                     // FP8: per z item and column, s_j(U) s_j(V)
     int32_t chunk_depth = 0;
     std::vector<int32_t> chunk_node;
     std::vector<int32_t> anc;                  // chunk x (chunk_depth + 1)
@@ -657,8 +729,10 @@ struct HostPlanMR {
 
 hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
                           int32_t storage, int32_t max_nrhs, HostPlanMR &hp) {
-    const bool f16 = storage == HMAT_STORE_FP16_SCALED;
-    const bool half = storage != HMAT_STORE_FP32;  // 16-bit codes (FP16 or BF16)
+    hp.fp8 = storage == HMAT_STORE_FP8 || storage == HMAT_STORE_FP8_F16D;
+    hp.dense_bf16 = storage == HMAT_STORE_FP8;
+    const bool f16 = storage == HMAT_STORE_FP16_SCALED || hp.fp8;  // D (and U, V unless FP8) block-scaled
+    const bool half = storage != HMAT_STORE_FP32;  // 16-bit lanes (FP16, BF16, or FP8 hi + lo pairs)
     hp.bf16 = storage == HMAT_STORE_BF16;
     hp.kb = half ? 32 : 16;
     hp.vw = half ? 8 : 4;
@@ -699,7 +773,7 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             } else {
                 const float au = col_major_amax(d.a, mt, d.rank, d.lda, &fin);
                 const float av = col_major_amax(d.b, ms, d.rank, d.ldb, &fin);
-                if (f16) {
+                if (f16 && !hp.fp8) {
                     hp.sU[b] = pow2_scale_f16(au);
                     hp.sV[b] = pow2_scale_f16(av);
                 }
@@ -707,6 +781,18 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             if (!fin) ok = false;
         });
         if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
+    }
+    if (hp.fp8) {
+        hp.colU.assign(nb, {});
+        hp.colV.assign(nb, {});
+        parallel_for(nb, [&](int64_t b) {
+            const hmat_block_desc &d = bl[b];
+            if (d.rank == 0) return;
+            hp.colU[b].resize(2 * (size_t)d.rank);
+            hp.colV[b].resize(2 * (size_t)d.rank);
+            e4m3_column_scales(d.a, t.size(d.target), d.rank, d.lda, hp.colU[b].data());
+            e4m3_column_scales(d.b, t.size(d.source), d.rank, d.ldb, hp.colV[b].data());
+        });
     }
     // chunks and their leaves (K-block aligned)
     int64_t xf = 0;
@@ -765,9 +851,17 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             nunit[s] = nu;
             for (int32_t g = 0; g < ngroups; ++g) {
                 const int32_t nm = std::min(4, (W - 64 * g + 15) / 16);
+                const int32_t lo_off = (int32_t)(hp.vlo.size() / 64);
+                if (hp.fp8)  // lo-scales of the group's 64 V columns (1 past the box's columns)
+                    for (int32_t c = 0; c < 64; ++c) {
+                        const int32_t col = 64 * g + c;
+                        hp.vlo.push_back(col < W ? f16_pow2_code(hp.colV[cm[col].first][2 * cm[col].second + 1])
+                                                 : f16_pow2_code(1.0));
+                    }
                 for (int32_t i = 0; i < nu; ++i) {
                     hmat::MRVUnit u{};
                     u.aoff = af;
+                    u.lo_off = hp.fp8 ? lo_off : 0;
                     u.c0 = c0 + i * kUnitChunks;
                     u.nc = std::min(kUnitChunks, c1 - u.c0);
                     u.nm = nm;
@@ -794,6 +888,12 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         z.vcol = vcol[b];
         z.rank = bl[b].rank;
         z.scale = hp.sU[b] * hp.sV[b];
+        z.col_off = 0;
+        if (hp.fp8) {
+            z.scale = 1.0f;
+            z.col_off = (int32_t)hp.zcol.size();
+            for (int32_t j = 0; j < bl[b].rank; ++j) hp.zcol.push_back(hp.colU[b][2 * j] * hp.colV[b][2 * j]);
+        }
         z.zoff = zf;
         zf += (int64_t)((bl[b].rank + KB - 1) / KB) * hp.ntmax;
         zitem_of[b] = (int32_t)hp.zitems.size();
@@ -833,6 +933,17 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         m.nseg = (int32_t)hp.segs.size() - m.seg_base;
         m.step_base = (int32_t)hp.ustep.size();
         m.nsteps = seg_kb;
+        m.ulo_base = (int32_t)hp.ulo.size();
+        m.nzsteps = 0;
+        for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
+            const hmat::MRSeg &sg = hp.segs[si];
+            if (sg.kind != 0) continue;
+            m.nzsteps += sg.nkb;
+            if (!hp.fp8) continue;
+            const int64_t b = hp.seg_block[si];
+            for (int32_t k = 0; k < sg.nkb * KB; ++k)  // lo-scales of the block's U columns, K-block by K-block
+                hp.ulo.push_back(f16_pow2_code(k < bl[b].rank ? hp.colU[b][2 * k + 1] : 1.0));
+        }
         const int64_t bbytes = KB == 32 ? 2048 : 1024;
         for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
             const hmat::MRSeg &sg = hp.segs[si];
@@ -904,6 +1015,7 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
                     T *fr = out + (af + (int64_t)kb * u.nm + ms) * 64 * vw;
                     for (int32_t l = 0; l < 64; ++l) {
                         const int32_t col = 64 * g + 16 * ms + l % 16;
+                        uint8_t hi[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int32_t e = 0; e < vw; ++e) {
                             const int32_t pr = kb * KB + vw * (l / 16) + e;
                             const int32_t gr = mr_row(hp, m, pr);
@@ -913,9 +1025,18 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
                                 const hmat_block_desc &d = bl[b];
                                 v = d.b[(gr - t.begin[s]) + (int64_t)cm[col].second * d.ldb];
                                 sc = hp.sV[b];
+                                if (hp.fp8) {
+                                    const float *cs = &hp.colV[b][2 * cm[col].second];
+                                    e4m3_hilo(v, cs[0], cs[1], &hi[e], &lo[e]);
+                                }
                             }
-                            fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
+                            if (!hp.fp8) fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
                         }
+                        if (hp.fp8)  // 8 hi codes, then 8 lo codes
+                            for (int32_t w = 0; w < 4; ++w) {
+                                fr[l * vw + w] = (T)(hi[2 * w] | (hi[2 * w + 1] << 8));
+                                fr[l * vw + 4 + w] = (T)(lo[2 * w] | (lo[2 * w + 1] << 8));
+                            }
                     }
                 }
             af += (int64_t)m.nkb * u.nm;
@@ -940,18 +1061,31 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
             const int32_t ncols = sg.kind == 0 ? d.rank : (int32_t)t.size(hp.seg_node[si]);
             const int32_t rbase = (int32_t)(sg.kind == 0 ? t.begin[d.target] : t.begin[tnode]);
             const float sc = sg.kind == 0 ? hp.sU[lb] : hp.sD[db];
+            const bool hilo = hp.fp8 && sg.kind == 0;
             for (int32_t kb = 0; kb < sg.nkb; ++kb)
                 for (int32_t ms = 0; ms < tl.nm; ++ms) {
                     T *fr = out + (af + (int64_t)kb * tl.nm + ms) * 64 * vw;
                     for (int32_t l = 0; l < 64; ++l) {
                         const int32_t tr = 16 * ms + l % 16;
+                        uint8_t hi[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int32_t e = 0; e < vw; ++e) {
                             const int32_t kk = kb * KB + vw * (l / 16) + e;
                             float v = 0.0f;
                             if (tr < tl.rows && kk < ncols)
                                 v = d.a[(tl.row0 + tr - rbase) + (int64_t)kk * d.lda];
-                            fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
+                            if (hilo) {
+                                if (kk < ncols) e4m3_hilo(v, hp.colU[lb][2 * kk], hp.colU[lb][2 * kk + 1], &hi[e], &lo[e]);
+                            } else if (hp.dense_bf16 && sg.kind == 1) {
+                                fr[l * vw + e] = (T)f32_to_bf16_rne(v * (1.0f / sc));  // BF16 of v / s_D
+                            } else {
+                                fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
+                            }
                         }
+                        if (hilo)  // 8 hi codes, then 8 lo codes
+                            for (int32_t w = 0; w < 4; ++w) {
+                                fr[l * vw + w] = (T)(hi[2 * w] | (hi[2 * w + 1] << 8));
+                                fr[l * vw + 4 + w] = (T)(lo[2 * w] | (lo[2 * w + 1] << 8));
+                            }
                     }
                 }
             af += (int64_t)sg.nkb * tl.nm;
@@ -1056,6 +1190,11 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
     if ((s = upload(h, hp.ustep, &p.ustep)) != HMAT_OK) return s;
+    if (hp.fp8) {
+        if ((s = upload(h, hp.vlo, &p.vlo)) != HMAT_OK) return s;
+        if ((s = upload(h, hp.ulo, &p.ulo)) != HMAT_OK) return s;
+        if ((s = upload(h, hp.zcol, &p.zcol)) != HMAT_OK) return s;
+    }
     void *vdev = nullptr, *uddev = nullptr;
     if ((s = dev_alloc(h, hp.v_frags * frag, &vdev)) != HMAT_OK) return s;
     if ((s = dev_alloc(h, hp.ud_frags * frag, &uddev)) != HMAT_OK) return s;
@@ -1081,6 +1220,10 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.num_vunits = (int32_t)hp.vunits.size();
     p.num_zitems = (int32_t)hp.zitems.size();
     p.num_tiles = (int32_t)hp.tiles.size();
+    p.max_nzsteps = 0;
+    for (const hmat::MRChunk &c : hp.chunks) p.max_nzsteps = std::max(p.max_nzsteps, c.nzsteps);
+    if (hp.fp8 && (int64_t)p.max_nzsteps * 32 * 2 * 4 > 65536)
+        return fail(HMAT_ERR_UNSUPPORTED, "FP8 form: a chunk's U lo-scale table exceeds the LDS budget");
     h->info.device_factor_bytes = (hp.v_frags + hp.ud_frags) * (int64_t)frag;
     h->info.workspace_bytes = (hp.x_frags + hp.z_frags) * (int64_t)bfrag + hp.part_floats * 4 +
                               (int64_t)(hp.chunks.size() + hp.zitems.size()) * hp.ntmax * 4;
@@ -1091,8 +1234,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
 hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t nb,
                         const hmat_options *opts, hmat_handle *h) {
     if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
-    if (opts->storage != HMAT_STORE_FP32 && opts->storage != HMAT_STORE_FP16_SCALED &&
-        opts->storage != HMAT_STORE_BF16)
+    if (opts->storage < HMAT_STORE_FP32 || opts->storage > HMAT_STORE_FP8_F16D)
         return fail(HMAT_ERR_INVALID_ARG, "unknown storage form");
     if (opts->max_nrhs < 1) return fail(HMAT_ERR_INVALID_ARG, "max_nrhs must be >= 1");
     if (opts->device < 0) return fail(HMAT_ERR_INVALID_ARG, "device must be >= 0");
@@ -1107,6 +1249,9 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     if (s != HMAT_OK) return s;
     HostPlan hp;
     HostPlanMR hpm;
+    const bool fp8 = opts->storage == HMAT_STORE_FP8 || opts->storage == HMAT_STORE_FP8_F16D;
+    if (fp8 && (opts->max_nrhs < 2 || fp64))
+        return fail(HMAT_ERR_UNSUPPORTED, "the FP8 storage forms need a multi-RHS handle (max_nrhs > 1, no flags)");
     h->mr = opts->max_nrhs > 1 && !fp64;
     s = h->mr ? build_plan_mr(t, st, blocks, nb, opts->storage, opts->max_nrhs, hpm)
               : build_plan(t, st, blocks, nb, opts->storage, acc_bytes, hp);
@@ -1165,8 +1310,14 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     in.num_dense_blocks = nd;
     in.num_lowrank_blocks = nl;
     in.stored_elements = elems;
-    const int64_t esz = opts->storage == HMAT_STORE_FP32 ? 4 : 2;
-    in.factor_bytes = elems * esz + (opts->storage == HMAT_STORE_FP16_SCALED ? 4 * (nd + 2 * nl) : 0);
+    const int64_t esz = opts->storage == HMAT_STORE_FP32 ? 4 : 2;  // FP8 forms: a hi + lo byte pair
+    int64_t scale_bytes = 0;
+    if (opts->storage == HMAT_STORE_FP16_SCALED) scale_bytes = 4 * (nd + 2 * nl);
+    if (fp8) {
+        scale_bytes = 4 * nd;  // one per dense block, then s_j and s'_j per U and V column
+        for (int64_t b = 0; b < nb; ++b) scale_bytes += 16 * (int64_t)blocks[b].rank;
+    }
+    in.factor_bytes = elems * esz + scale_bytes;
     in.device_factor_bytes = (hp.v_elems + hp.ud_elems) * esz;
     in.workspace_bytes = (hp.part_floats + hp.slice_floats + hp.zg_floats) * acc_bytes;
     in.storage = opts->storage;

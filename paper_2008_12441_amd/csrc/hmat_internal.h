@@ -121,7 +121,9 @@ struct DevPlan {
 //  * Fragments: an A fragment is 16 rows x KB inner indices, stored as 64
 //    lanes x 16 bytes (1 KiB): lane l holds row l % 16 and the VW consecutive
 //    inner indices VW * (l / 16) + [0, VW) of that row (FP32: KB = 16, VW = 4,
-//    fed to four 16x16x4 steps; FP16: KB = 32, VW = 8, one 16x16x32 step).
+//    fed to four 16x16x4 steps; FP16/BF16: KB = 32, VW = 8, one 16x16x32 step;
+//    FP8 forms: KB = 32, VW = 8, the lane's 16 bytes are 8 hi codes then 8 lo
+//    codes of U or V, or 8 BF16/FP16 codes of D, all fed as FP16).
 //    A B fragment is KB inner indices x 16 columns with the mirrored lane
 //    mapping (lane l: column l % 16, inner indices VW * (l / 16) + [0, VW)),
 //    1 KiB for FP32, 2 KiB for FP16 (a high and a low half-precision part).
@@ -150,6 +152,8 @@ struct MRChunk {
     int64_t xoff;         // first B fragment of its Xpack (relative to xpack)
     int32_t step_base;    // first entry of its U-phase step table
     int32_t nsteps;       // K-block steps over all its segments
+    int32_t ulo_base;     // FP8 forms: first of its 32 x nzsteps U lo-scales in ulo
+    int32_t nzsteps;      // steps over z segments (they come first)
 };
 
 struct MRLeaf {
@@ -164,7 +168,7 @@ struct MRVUnit {
     int32_t c0;           // first chunk
     int32_t nc;           // chunks
     int32_t nm;           // m-subtiles (16 columns each), 1..4
-    int32_t pad_;
+    int32_t lo_off;       // FP8 forms: first of its 64 V lo-scales in vlo
     int64_t poff;         // offset of its partial sums (floats)
 };
 
@@ -174,7 +178,7 @@ struct MRZItem {          // one low-rank block (t, s)
     int32_t vcol;         // first column of the block among the columns of (level, s)
     int32_t rank;
     float scale;          // product of the U and V scales
-    int32_t pad_;
+    int32_t col_off;      // FP8 forms: first of its `rank` per-column scales in zcol
     int64_t zoff;         // first B fragment of its Zpack
 };
 
@@ -211,6 +215,8 @@ struct DevPlanMR {
     int32_t num_vunits;
     int32_t num_zitems;
     int32_t num_tiles;
+    int32_t max_nzsteps;      // most z steps of a chunk (FP8 forms: U lo-scale table size / 32)
+    int32_t pad_;
     const void *V;            // A fragments
     const void *UD;
     void *xpack;              // B fragments of X (in the same allocation as zpack, after it)
@@ -227,6 +233,10 @@ struct DevPlanMR {
     const MRTile *tiles;
     const MRStep *ustep;      // per chunk step (MRChunk::step_base)
     const float *scales;      // n-tile scales: sz rows (one per z item), then sx rows (one per chunk)
+    // FP8 forms
+    const uint16_t *vlo;      // FP16 lo-scales s'_j of V columns, 64 per unit column group
+    const uint16_t *ulo;      // FP16 lo-scales s'_j of U columns, 32 per z step of each chunk
+    const float *zcol;        // per z item and column: s_j of U times s_j of V
 };
 
 // ---------------------------------------------------------------------------

@@ -59,6 +59,8 @@ struct MR<HMAT_STORE_FP32> {
     static constexpr int BFRAG = 64;  // 16-byte lane slots per B fragment
     static constexpr bool SCALED = false;
     using A = f32x4;
+    using Op = A;
+    static constexpr bool FP8 = false;
     struct B {
         f32x4 v;
     };
@@ -88,6 +90,8 @@ struct MR<HMAT_STORE_FP16_SCALED> {
     static constexpr int BFRAG = 128;  // hi (64 slots) then lo (64 slots)
     static constexpr bool SCALED = true;
     using A = f16x8;
+    using Op = A;
+    static constexpr bool FP8 = false;
     struct B {
         f16x8 hi, lo;
     };
@@ -126,6 +130,8 @@ struct MR<HMAT_STORE_BF16> {
     static constexpr int BFRAG = 128;   // hi (64 slots) then lo (64 slots)
     static constexpr bool SCALED = false;  // BF16 keeps FP32's exponent range
     using A = bf16x8;
+    using Op = A;
+    static constexpr bool FP8 = false;
     struct B {
         bf16x8 hi, lo;
     };
@@ -156,6 +162,95 @@ struct MR<HMAT_STORE_BF16> {
     }
 };
 
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+// FP8 forms: U and V fragments hold per lane 8 E4M3 hi codes then 8 lo codes
+// (OCP E4M3FN, converted exactly by the hardware), D fragments 8 BF16 codes
+// (DBF16) or 8 FP16 codes; every A fragment reaches the MFMA as FP16, against
+// FP16 hi + lo activations as in the FP16 form.
+template <bool DBF16>
+struct MRFp8 {
+    static constexpr int KB = 32;
+    static constexpr int VW = 8;
+    static constexpr int BFRAG = 128;  // hi (64 slots) then lo (64 slots)
+    static constexpr bool SCALED = true;
+    static constexpr bool FP8 = true;
+    using A = u32x4;                   // the lane's raw 16 bytes
+    using Op = f16x8;
+    struct B {
+        f16x8 hi, lo;
+    };
+    __device__ static inline A loadA(rsrc_t r, int soff, int lane) {
+        return __builtin_bit_cast(u32x4, buf16<kNontemporal>(r, lane * 16, soff));
+    }
+    __device__ static inline B loadB(rsrc_t r, int soff, int lane) {
+        B b;
+        b.hi = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16, soff));
+        b.lo = __builtin_bit_cast(f16x8, buf16<0>(r, lane * 16 + 1024, soff));
+        return b;
+    }
+    __device__ static inline void storeB(void *base, int64_t frag, int lane, const float (&v)[VW]) {
+        f16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            hi[e] = (_Float16)v[e];
+            lo[e] = (_Float16)(v[e] - (float)hi[e]);
+        }
+        f16x8 *p = static_cast<f16x8 *>(base) + frag * BFRAG + lane;
+        p[0] = hi;
+        p[64] = lo;
+    }
+    // RNE_f16(hi + s' lo) for the lane's 8 elements; s2[q] holds the lo
+    // scales of elements 2q and 2q + 1. Both conversions are exact, so the
+    // fused multiply-add rounds once.
+    __device__ static inline Op hilo(const A &r, const h2 (&s2)[4]) {
+        Op o;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const h2 h0 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(r[w], 1.0f, false);
+            const h2 h1 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(r[w], 1.0f, true);
+            const h2 l0 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(r[2 + w], 1.0f, false);
+            const h2 l1 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(r[2 + w], 1.0f, true);
+            const h2 v0 = __builtin_elementwise_fma(l0, s2[2 * w], h0);
+            const h2 v1 = __builtin_elementwise_fma(l1, s2[2 * w + 1], h1);
+            o[4 * w] = v0[0];
+            o[4 * w + 1] = v0[1];
+            o[4 * w + 2] = v1[0];
+            o[4 * w + 3] = v1[1];
+        }
+        return o;
+    }
+    // D codes as FP16 (BF16 -> FP16 is exact for |value| >= 2^-14)
+    __device__ static inline Op dense(const A &r) {
+        if constexpr (DBF16) {
+            Op o;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                o[2 * w] = (_Float16)__builtin_bit_cast(float, r[w] << 16);
+                o[2 * w + 1] = (_Float16)__builtin_bit_cast(float, r[w] & 0xffff0000u);
+            }
+            return o;
+        } else {
+            return __builtin_bit_cast(Op, r);
+        }
+    }
+    __device__ static inline void mma(const Op &a, const B &b, f32x4 &c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b.lo, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct MR<HMAT_STORE_FP8> : MRFp8<true> {};
+template <>
+struct MR<HMAT_STORE_FP8_F16D> : MRFp8<false> {};
+
+// Forms whose fragments feed the MFMA as loaded.
+template <int STORE>
+struct IsFp8 {
+    static constexpr bool value = STORE == HMAT_STORE_FP8 || STORE == HMAT_STORE_FP8_F16D;
+};
+
 // power of two with |v| / s <= 2^14 for |v| <= amax (1 for amax == 0)
 __device__ inline float col_scale(float amax) {
     if (!(amax > 0.0f)) return 1.0f;
@@ -179,6 +274,9 @@ __device__ inline float wave_max(float v) {
 // whenever those change, the accumulators are moved to the new scales
 // (powers of two, so the move is exact). info is called in increasing s.
 //
+// prep(a, m, info(s)) turns a loaded A fragment into the MFMA operand (the
+// FP8 forms dequantise there; the other forms pass it through).
+//
 // Scales are read through the scalar cache from info(s).srow, which requires
 // them to stay unchanged during the launch. With LANE_SCALES (one n-tile) the
 // caller instead loads the scales the wave needs into sv, one per lane, after
@@ -189,11 +287,13 @@ struct StepInfo {
     const float *srow;   // n-tile scales of the step's B (scaled form), read through the scalar cache
     float fac;           // extra power-of-two factor of those scales
     int32_t sidx;        // LANE_SCALES: lane of sv holding the step's scale (srow unused)
+    int32_t dense;       // FP8 forms: the step multiplies D (else U or V)
+    int32_t lofs;        // FP8 forms, U steps: offset of the step's 32 lo-scales in the wave's LDS table
 };
 
-template <int STORE, int NT, bool LANE_SCALES, class Info>
+template <int STORE, int NT, bool LANE_SCALES, class Info, class Prep>
 __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int nm, int nsteps, int lane, Info info,
-                                  f32x4 (&acc)[4][NT], float (&scur)[NT], float sv) {
+                                  Prep prep, f32x4 (&acc)[4][NT], float (&scur)[NT], float sv) {
     using F = MR<STORE>;
     static_assert(!LANE_SCALES || NT == 1, "lane scales hold one n-tile");
     auto scale_of = [&](const StepInfo &i, int t) {
@@ -247,9 +347,11 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            if (m < nm)
+            if (m < nm) {
+                const typename F::Op op = prep(a[m], m, ic);  // the fragment as the MFMA takes it
 #pragma unroll
-                for (int t = 0; t < NT; ++t) F::mma(a[m], b[t], acc[m][t]);
+                for (int t = 0; t < NT; ++t) F::mma(op, b[t], acc[m][t]);
+            }
         load_a(a, st + 4);
         ic = in_;
         if (F::SCALED) {
@@ -350,6 +452,22 @@ __device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
     for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
     float sv = 1.0f;  // lane j: n-tile scale of the unit's chunk j
     if (LANE_SCALES && F::SCALED && lane < u.nc) sv = p.sx[(int64_t)(u.c0 + lane) * p.ntmax];
+    h2 vl[4];  // FP8 forms: lo-scale of the lane's V column in each m-subtile, twice
+    if constexpr (F::FP8) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const _Float16 sl = __builtin_bit_cast(_Float16, p.vlo[(int64_t)u.lo_off * 64 + 16 * m + (lane & 15)]);
+            vl[m] = h2{sl, sl};
+        }
+    }
+    auto prep = [&](const typename F::A &a, int m, const StepInfo &) -> typename F::Op {
+        if constexpr (F::FP8) {
+            const h2 s2[4] = {vl[m], vl[m], vl[m], vl[m]};
+            return F::hilo(a, s2);
+        } else {
+            return a;
+        }
+    };
     int c = u.c0 - 1, cend = 0;  // chunk of the step asked for last, and the step where it ends
     const int64_t ntm = p.ntmax;
     auto info = [&](int st) {
@@ -358,9 +476,9 @@ __device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
             cend += cload(p.chunks, c).nkb;
         }
         return StepInfo{(b0 + (int64_t)st * ntm) * bbytes, LANE_SCALES ? nullptr : p.sx + (int64_t)c * ntm, 1.0f,
-                        LANE_SCALES ? c - u.c0 : 0};
+                        LANE_SCALES ? c - u.c0 : 0, 0, 0};
     };
-    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, acc, scur, sv);
+    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, prep, acc, scur, sv);
     float *out = p.part + u.poff;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -397,7 +515,9 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
             a1 += src[(int64_t)(i + 1) * ustride];
         }
         if (i < z.nu) a0 += src[(int64_t)i * ustride];
-        const float s = (a0 + a1) * z.scale;
+        float zsc = z.scale;
+        if constexpr (F::FP8) zsc = p.zcol[z.col_off + j];  // s_j of U times s_j of V
+        const float s = (a0 + a1) * zsc;
         zs[j][nn] = s;
         amax = fmaxf(amax, fabsf(s));
     }
@@ -425,7 +545,7 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
 // ---------------------------------------------------------------------------
 template <int STORE, int NT, bool LANE_SCALES>
 __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float alpha, float beta,
-                               float *__restrict__ y, int64_t ldy) {
+                               float *__restrict__ y, int64_t ldy, uint32_t *lo_lds) {
     using F = MR<STORE>;
     const MRTile tl = cload(p.tiles, w);
     const MRChunk ch = cload(p.chunks, tl.chunk);
@@ -447,12 +567,30 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
         const MRSeg sg = p.segs[ch.seg_base + lane];  // per lane: a vector load
         sv = sg.kind == 0 ? p.sz[(int64_t)sg.sidx * p.ntmax] : p.sx[(int64_t)sg.sidx * p.ntmax];
     }
+    if constexpr (F::FP8) {  // the chunk's U lo-scales, 32 per z step, into this wave's LDS table
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
+        for (int i = lane; i < ch.nzsteps * 16; i += 64) lo_lds[i] = src[i];
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+    }
     auto info = [&](int st) {
         const MRStep e = cload(steps, st);
         return StepInfo{e.bofs, LANE_SCALES ? nullptr : p.scales + (int64_t)e.srow * p.ntmax,
-                        e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f, LANE_SCALES ? e.lseg : 0};
+                        e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f, LANE_SCALES ? e.lseg : 0, e.sleaf >= 0 ? 1 : 0,
+                        st * 32};
     };
-    mfma_steps<STORE, NT, LANE_SCALES>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, acc, scur, sv);
+    auto prep = [&](const typename F::A &a, int, const StepInfo &si) -> typename F::Op {
+        if constexpr (F::FP8) {
+            if (si.dense) return F::dense(a);
+            // the 8 lo-scales of the lane's K indices of this step
+            const h2 *q = reinterpret_cast<const h2 *>(lo_lds) + (si.lofs + 8 * (lane >> 4)) / 2;
+            const h2 s2[4] = {q[0], q[1], q[2], q[3]};
+            return F::hilo(a, s2);
+        } else {
+            return a;
+        }
+    };
+    mfma_steps<STORE, NT, LANE_SCALES>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, prep, acc, scur, sv);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll

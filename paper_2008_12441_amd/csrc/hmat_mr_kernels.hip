@@ -52,9 +52,11 @@ __global__ __launch_bounds__(256) void k_zmfma(DevPlanMR p, int nt_used) {
 template <int STORE, int NT>
 __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_umfma(DevPlanMR p, int k, float alpha, float beta,
                                                                      float *__restrict__ y, int64_t ldy) {
+    extern __shared__ __align__(16) uint32_t lo_tables[];  // FP8 forms: 16 x max_nzsteps words per wave
     const int w = wave_id_xcd(4);
     if (w >= p.num_tiles) return;
-    mr_tile<STORE, NT, false>(p, w, threadIdx.x & 63, k, alpha, beta, y, ldy);
+    mr_tile<STORE, NT, false>(p, w, threadIdx.x & 63, k, alpha, beta, y, ldy,
+                              lo_tables + (threadIdx.x >> 6) * 16 * p.max_nzsteps);
 }
 
 template <int STORE, int NT>
@@ -74,7 +76,8 @@ int launch_mr_nt(const DevPlanMR &p, int32_t k, float alpha, const float *x, int
         if ((e = (int)hipGetLastError())) return e;
     }
     if (mark) mark(ctx, 2);
-    hipLaunchKernelGGL((k_umfma<STORE, NT>), dim3((p.num_tiles + 3) / 4), dim3(256), 0, st, p, k, alpha, beta, y,
+    const size_t lds = IsFp8<STORE>::value ? (size_t)4 * 64 * p.max_nzsteps : 0;
+    hipLaunchKernelGGL((k_umfma<STORE, NT>), dim3((p.num_tiles + 3) / 4), dim3(256), lds, st, p, k, alpha, beta, y,
                        ldy);
     if ((e = (int)hipGetLastError())) return e;
     if (mark) mark(ctx, 3);
@@ -105,6 +108,10 @@ int launch_mr(const DevPlanMR &p, int32_t k, float alpha, const float *x, int64_
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.storage == HMAT_STORE_FP16_SCALED)
         return launch_mr_form<HMAT_STORE_FP16_SCALED>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
+    if (p.storage == HMAT_STORE_FP8)
+        return launch_mr_form<HMAT_STORE_FP8>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
+    if (p.storage == HMAT_STORE_FP8_F16D)
+        return launch_mr_form<HMAT_STORE_FP8_F16D>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
     if (p.storage == HMAT_STORE_BF16)
         return launch_mr_form<HMAT_STORE_BF16>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);
     return launch_mr_form<HMAT_STORE_FP32>(p, k, alpha, x, ldx, beta, y, ldy, st, mark, ctx);

@@ -253,3 +253,15 @@ def test_batch_entry_points_validate_before_device_calls():
     info = hm.binding.hmat_batch_info()
     assert lib.hmat_batch_get_info(nb, ctypes.byref(info)) == 1
     assert lib.hmat_batch_autotune(nb, 1.0, p, ld, 0.0, p, ld, None, None, 1, None) == 1
+
+
+def test_fp8_forms_need_multi_rhs_handles(small):
+    tree, blocks, keep = descriptors(small)
+    for form in (hm.binding.HMAT_STORE_FP8, hm.binding.HMAT_STORE_FP8_F16D):
+        st, msg = _create_status(tree, blocks, storage=form, max_nrhs=1)
+        assert st == 4 and "multi-RHS" in msg, (st, msg)
+        st, msg = _create_status(tree, blocks, storage=form, max_nrhs=8, flags=1)
+        assert st == 4, (st, msg)
+        st, msg = _create_status(tree, blocks, storage=form, max_nrhs=8)
+        assert st not in (1, 4), msg      # valid: fails only at the device stage on a machine without a GPU
+    assert _create_status(tree, blocks, storage=5)[0] == 1

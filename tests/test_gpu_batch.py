@@ -244,6 +244,11 @@ def test_batch_validation_and_lifetime():
         with pytest.raises(hm.HmatError) as e:
             hm.HBatch(members, ks)
         assert e.value.status == hm.binding.HMAT_ERR_INVALID_ARG, (ks, str(e.value))
+    f8 = create(d1, storage="fp8", max_nrhs=4)
+    with pytest.raises(hm.HmatError) as e:
+        hm.HBatch([f8], [4])
+    assert e.value.status == hm.binding.HMAT_ERR_UNSUPPORTED
+    f8.close()
     b = hm.HBatch([s1, s2, m1], [1, 1, 16])
     with pytest.raises(hm.HmatError) as e:
         hm.hmat_destroy(s1.handle)          # still referenced by the batch

@@ -15,7 +15,7 @@ import pytest
 import oracle
 from oracle.quant import dequantised
 from hmat_inputs import build_tree, make_hmatrix, make_rhs, uniform_tree
-from hmat_testlib import assert_close, assert_fp32_rounding_of, create, gpu_matvec
+from hmat_testlib import assert_close, assert_fp32_rounding_of, create, gpu_matvec, rel_err_cols
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ ELEM_TOL = 1e-4
 # The multi-RHS BF16 form feeds MFMA with activations split into two BF16
 # parts (16 significant bits), so its own arithmetic error is ~2^-16 relative
 # per product instead of ~2^-22 for the FP16 hi+lo split.
-KERNEL_TOL = {"fp32": 1e-5, "fp16": 1e-5, "bf16": 3e-5}
+KERNEL_TOL = {"fp32": 1e-5, "fp16": 1e-5, "bf16": 3e-5, "fp8": 1e-5, "fp8_f16d": 1e-5}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -214,7 +214,7 @@ def _tree_for(shape):
 
 
 @pytest.mark.parametrize("name,shape,r,method,k", MR_CASES, ids=[c[0] for c in MR_CASES])
-@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16", "fp8", "fp8_f16d"])
 def test_multi_rhs(name, shape, r, method, k, form):
     _log(f"case multi-rhs {name} {form}")
     kind = "log" if len(shape) == 2 else "inv"
@@ -227,6 +227,9 @@ def test_multi_rhs(name, shape, r, method, k, form):
     assert_close(y, ref, KERNEL_TOL[form], 10 * KERNEL_TOL[form])
     if form == "fp16":
         assert_close(y, oracle.oracle_matvec(data, x), 1e-3)
+    elif form.startswith("fp8"):   # the form's own quantisation error is reported, not gated
+        ref0 = oracle.oracle_matvec(data, x)
+        _log(f"{form} error vs canonical oracle {np.max(rel_err_cols(y, ref0)):.3e}")
 
 
 @pytest.mark.parametrize("form", ["fp32", "fp16"])
@@ -257,7 +260,7 @@ def c3_random():
     return data
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16", "fp8", "fp8_f16d"])
 def test_c3_full_size_multi_rhs(c3_random, form):
     data = c3_random
     _log(f"case c3 {form} full size, 64 RHS")

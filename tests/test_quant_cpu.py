@@ -1,8 +1,10 @@
 """The library's host quantisers bit-match independent library casts.
 
 FP16 (round to nearest even) against numpy's float16 cast, BF16 against
-torch's CPU bfloat16 cast, and the power-of-two scale rule
-s = 2^(ceil(log2 amax) - 15) against its definition.
+torch's CPU bfloat16 cast, E4M3 against torch's float8_e4m3fn cast, the
+power-of-two scale rules s = 2^(ceil(log2 amax) - 15) and
+s = 2^ceil(log2(amax / 448)) against their definitions, and the FP8 hi + lo
+column split against the oracle's independent implementation.
 """
 import os
 import subprocess
@@ -76,3 +78,75 @@ def test_pow2_scale_rule(probe):
             c -= 1
         assert sc == 2.0 ** max(c - 15, -126)
         assert amax / sc <= 2.0 ** 15
+
+
+def _run_mode(exe, mode, payload):
+    return subprocess.run([exe, mode], input=payload, capture_output=True, check=True,
+                          env={**os.environ, "LD_LIBRARY_PATH": "/opt/rocm/lib"}).stdout
+
+
+def _e4m3_values():
+    rng = np.random.default_rng(3)
+    v = [rng.uniform(-448, 448, 20000), rng.standard_normal(20000) * 10.0 ** rng.uniform(-4, 2.6, 20000)]
+    # every code's value, the midpoints between neighbours (ties), and the subnormal range
+    import torch
+
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    codes = np.sort(codes[np.isfinite(codes) & (codes >= 0)])
+    mids = (codes[1:] + codes[:-1]) / 2
+    v += [codes, -codes, mids, -mids, rng.uniform(0, 2.0 ** -6, 5000)]
+    vals = np.concatenate(v)
+    vals = vals[np.abs(vals) <= 448.0]
+    return vals.astype(np.float32)
+
+
+def test_e4m3_matches_torch(probe):
+    import torch
+
+    vals = _e4m3_values()
+    out = _run_mode(probe, "e4m3", vals.tobytes())
+    rec = np.frombuffer(out, dtype=np.dtype([("c", "u1"), ("s", "<f8")]))
+    ref = torch.from_numpy(vals).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    bad = np.nonzero(rec["c"] != ref)[0]
+    assert len(bad) == 0, [(float(vals[i]), int(rec["c"][i]), int(ref[i])) for i in bad[:5]]
+
+
+def test_e4m3_scale_rule(probe):
+    rng = np.random.default_rng(4)
+    a = np.concatenate([np.abs(rng.standard_normal(5000)) * 10.0 ** rng.uniform(-30, 30, 5000),
+                        448.0 * 2.0 ** np.arange(-60, 60), 448.0 * 2.0 ** np.arange(-60, 60) * 1.0000001,
+                        [0.0]]).astype(np.float32)
+    out = _run_mode(probe, "e4m3", a.tobytes())
+    s = np.frombuffer(out, dtype=np.dtype([("c", "u1"), ("s", "<f8")]))["s"]
+    for amax, sc in zip(a.astype(np.float64), s):
+        if amax == 0:
+            assert sc == 1.0
+            continue
+        assert amax / sc <= 448.0 < 2 * amax / sc, (amax, sc)
+        assert sc == 2.0 ** round(np.log2(sc))
+
+
+def test_fp8_column_split_matches_oracle(probe):
+    """Column scales and hi/lo codes: the library's host split against the
+    oracle's dequantiser, value for value."""
+    import torch
+
+    from oracle.quant import _dequant_fp8_columns
+
+    rng = np.random.default_rng(5)
+    rows, cols = 300, 24
+    a = rng.standard_normal((rows, cols)) * 10.0 ** rng.uniform(-6, 3, cols)[None, :]
+    a[:, 3] = 0.0                                   # an all-zero column
+    a[:, 5] = 448.0 * 2.0 ** -10                    # every element exact in E4M3 (r = 0)
+    a = a.astype(np.float32)
+    flat = np.asfortranarray(a).reshape(-1, order="F")
+    payload = np.array([rows, cols], np.int32).tobytes() + flat.astype(np.float32).tobytes()
+    out = _run_mode(probe, "fp8col", payload)
+    sc = np.frombuffer(out[:8 * cols], dtype="<f4").reshape(cols, 2).astype(np.float64)
+    hl = np.frombuffer(out[8 * cols:], dtype="u1").reshape(cols, rows, 2)
+    hi = torch.from_numpy(np.ascontiguousarray(hl[:, :, 0])).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    lo = torch.from_numpy(np.ascontiguousarray(hl[:, :, 1])).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    dev = sc[:, :1] * (hi + sc[:, 1:] * lo).astype(np.float16).astype(np.float64)   # columns x rows
+    ref = _dequant_fp8_columns(flat, rows, cols).reshape(cols, rows).astype(np.float64)
+    assert np.array_equal(dev.astype(np.float32), ref.astype(np.float32))
+    assert sc[3, 0] == 1.0 and sc[3, 1] == 1.0 and sc[5, 1] == 1.0
