@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--c4-steps", type=int, default=20)
     ap.add_argument("--c4-members", type=int, default=256)
     ap.add_argument("--c4-method", default="random", help="factor fill of the batched members")
+    ap.add_argument("--no-c5", action="store_true", help="skip the large 3D (128^3, 128 RHS) storage-form leg")
+    ap.add_argument("--c5-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -104,16 +106,28 @@ def probe_bandwidth(stream, nbytes=4 << 30, reps=5):
     return read_gbps, copy_gbps
 
 
+SV_SOURCES = ("hmat_kernels.hip", "hmat_sv_device.h", "hmat_device_common.h", "hmat_internal.h")
+
+
+def kernel_source_digest():
+    """First 16 hex digits of the sha256 over the sources of the single-vector kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in SV_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2008_12441_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile(kernel_key):
     """HBM bytes per launch from the committed counter summary, or None when the
     kernel source changed after the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "c2_fp32_hbm_traffic.json")
-    src = os.path.join(ROOT, "paper_2008_12441_amd", "csrc", "hmat_kernels.hip")
     try:
         prof = json.load(open(path))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        digest = kernel_source_digest()
     except (OSError, ValueError):
         return None
     if prof.get("kernel") != kernel_key or prof.get("kernel_source_sha256_16") != digest:
@@ -232,7 +246,68 @@ def run_batched(stream, steps, warmup, count=256, method="random", with_oracle=T
     return out
 
 
-def run_multi_rhs(stream, steps, warmup, with_oracle=True):
+def run_large_3d(stream, steps, warmup, with_oracle=True, forms=("fp32", "fp16", "fp8", "fp8_f16d"), method=None):
+    """3D 128^3 grid (N = 2^21), 1/r kernel, rank 32, 128 RHS: the storage forms
+    on the multi-RHS (MFMA) path, FP8 hi + lo U/V with BF16 dense blocks against
+    FP32 on the same GPU. Errors are taken on the first 4 right-hand sides."""
+    import torch
+
+    import paper_2008_12441_amd as hm
+    from hmat_inputs import WORKLOADS, build_workload
+
+    w = WORKLOADS["c5"]
+    t0 = time.time()
+    data, x = build_workload("c5", device="cuda", method=method)
+    log(f"setup c5 ({w.describe()}): {time.time() - t0:.1f} s")
+    n, k = data.n, w.nrhs
+    t = data.tree
+    tree, blocks, keep = hm.make_descriptors(t.parent, t.begin, t.end, data.blocks.target, data.blocks.source,
+                                             data.blocks.rank, data.pool, data.off_a, data.off_b)
+    xd = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    flops = 2.0 * data.pool.size * k
+    vec_bytes = 2 * n * k * 4
+    out = {"workload": f"c5: {w.describe()}", "nrhs": k, "alg_flops_per_step": flops,
+           "stored_elements": int(data.pool.size)}
+    ys = {}
+    for form in forms:
+        t1 = time.time()
+        h = hm.HMatrix(tree, blocks, storage=form, max_nrhs=k)
+        log(f"c5 {form}: hmat_create {time.time() - t1:.1f} s")
+        yd = torch.empty_like(xd)
+        ms, ph = time_matvecs(h, xd, yd, steps, warmup, stream, k=k)
+        ys[form] = yd[:4].cpu().numpy().T.astype(np.float64)
+        b = h.info["factor_bytes"] + vec_bytes
+        out[form] = {"ms_per_step": round(ms, 4), "GBps": round(b / (ms * 1e-3) / 1e9, 1),
+                     "TFLOPps": round(flops / (ms * 1e-3) / 1e12, 2), "alg_bytes_per_step": b,
+                     "phases_ms": [round(v, 4) for v in ph]}
+        log(f"c5 {form}: {ms:.3f} ms per {k}-RHS product, {out[form]['GBps']} GB/s, {out[form]['TFLOPps']} TFLOP/s")
+        h.close()
+        del yd
+        torch.cuda.empty_cache()
+    base = out["fp32"]["ms_per_step"] if "fp32" in out else None
+    for form in forms:
+        if base and form != "fp32":
+            out[form]["speedup_vs_fp32"] = round(base / out[form]["ms_per_step"], 3)
+    if "fp32" in out:
+        out["roofline_fp32"] = {"bound": "mfma", "peak": 157.3, "unit": "TFLOP/s",
+                                "frac": round(out["fp32"]["TFLOPps"] / 157.3, 4)}
+    if "fp8" in out:
+        out["roofline_fp8"] = {"bound": "hbm", "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                               "frac": round(out["fp8"]["GBps"] / HBM_PEAK_GBPS, 4)}
+    if with_oracle:
+        import oracle
+
+        t1 = time.time()
+        ref = oracle.oracle_matvec(data, x[:, :4])
+        log(f"c5 oracle (4 RHS): {time.time() - t1:.1f} s")
+        for form in forms:
+            e = np.linalg.norm(ys[form] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            out[form]["rel_err_vs_fp64_oracle_max_col"] = float(e.max())
+        out["error_sample"] = "first 4 right-hand sides, FP64 oracle over the canonical FP32 factors"
+    return out
+
+
+def run_multi_rhs(stream, steps, warmup, with_oracle=True, method=None):
     """3D 64^3 grid (N = 262144), 1/r kernel, rank 64, 64 RHS: FP32 vs FP16 storage on MFMA."""
     import torch
 
@@ -241,7 +316,7 @@ def run_multi_rhs(stream, steps, warmup, with_oracle=True):
 
     w = WORKLOADS["c3"]
     t0 = time.time()
-    data, x = build_workload("c3", device="cuda")
+    data, x = build_workload("c3", device="cuda", method=method)
     log(f"setup c3 ({w.describe()}): {time.time() - t0:.1f} s")
     n, k = data.n, w.nrhs
     t = data.tree
@@ -423,7 +498,17 @@ def main():
         del keep, tree, blocks, data
         gc.collect()
         torch.cuda.empty_cache()
-        result["multi_rhs_c3"] = run_multi_rhs(stream, args.c3_steps, 3, with_oracle=not args.no_cpu_baseline)
+        result["multi_rhs_c3"] = run_multi_rhs(stream, args.c3_steps, 3, with_oracle=not args.no_cpu_baseline,
+                                               method=args.method)
+    if not args.no_c5:
+        import gc
+
+        import torch
+
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["large_3d_c5"] = run_large_3d(stream, args.c5_steps, 2, with_oracle=not args.no_cpu_baseline,
+                                             method=args.method)
     if not args.no_c4:
         import gc
 
