@@ -132,9 +132,9 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
             if (it.kind == BK_SV) {
                 for (int j = wave; j < it.count; j += 4) sv_vtile<STORE, float>(p, it.first + j, lane, ar.x);
             } else if (it.kind == BK_SZ1) {
-                for (int j = wave; j < it.count; j += 4) sv_z1<float>(p, it.first + j, lane);
+                sv_z1_packed<float>(p, it.first, it.count, it.lanes, wave, lane);
             } else if (it.kind == BK_SZ2) {
-                for (int j = wave; j < it.count; j += 4) sv_z2<float>(p, it.first + j, lane);
+                sv_z2_packed<float>(p, it.first, it.count, it.lanes, wave, lane);
             } else {
                 for (int j = 0; j < it.count; ++j) {
                     if (j) __syncthreads();  // the previous chunk's operand is still being read from LDS
@@ -146,11 +146,10 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
         if (HAS_M && it.kind >= BK_MX) {
             const DevPlanMR p = load_plan_mr(&a.members[it.member].mp);
             if (it.kind == BK_MX) {
-                float(*red)[17] = reinterpret_cast<float(*)[17]>(lds);
-                float *sig = reinterpret_cast<float *>(lds) + 16 * 17;
+                float *red = reinterpret_cast<float *>(lds);
                 for (int j = 0; j < it.count; ++j) {
-                    if (j) __syncthreads();  // red and sig are reused
-                    mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, red, sig);
+                    if (j) __syncthreads();  // red is reused
+                    mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, red);
                 }
             } else if (it.kind == BK_MV) {
                 for (int j = wave; j < it.count; j += 4) mr_vunit<STORE, 1, true>(p, it.first + j, lane);

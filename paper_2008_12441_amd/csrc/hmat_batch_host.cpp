@@ -117,8 +117,14 @@ std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i, double g
     if (!h->mr) {
         const hmat::DevPlan &p = h->plan;
         const int32_t nsv = stage(hmat::BK_SV, p.num_vtiles, h->cost_src, -1, 0, c0);
+        const size_t z0 = out.size();
         const int32_t nz1 = stage(hmat::BK_SZ1, p.num_z1, h->cost_z1, nsv ? c0 : -1, nsv, c0 + 1);
         const int32_t nz2 = stage(hmat::BK_SZ2, p.num_z2, h->cost_z2, c0 + 1, nz1, c0 + 2);
+        // reduction items carry the lanes per unit: the member's largest rank rounded up to a power of
+        // two (a wave then works on 64 / that many units at once)
+        int32_t lanes = 1;
+        while (lanes < std::min(h->max_rank, 64)) lanes *= 2;
+        for (size_t i = z0; i < out.size(); ++i) out[i].it.lanes = lanes;
         int32_t dep = -1, need = 0;
         if (nz2) dep = c0 + 2, need = nz2;
         else if (nz1) dep = c0 + 1, need = nz1;
@@ -127,7 +133,7 @@ std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i, double g
     } else {
         const hmat::DevPlanMR &p = h->mrp;
         std::vector<float> xcost(p.num_chunks);
-        for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2;
+        for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2 + 16384.0f;
         const int32_t nmx = stage(hmat::BK_MX, p.num_chunks, xcost, -1, 0, c0);
         const int32_t nmv = stage(hmat::BK_MV, p.num_vunits, h->cost_src, c0, nmx, c0 + 1);
         const int32_t nmz = stage(hmat::BK_MZ, p.num_zitems, h->cost_z1, nmv ? c0 + 1 : c0, nmv ? nmv : nmx, c0 + 2);
@@ -292,8 +298,8 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
     }
     b->zs_rank = (b->zs_rank + 3) / 4 * 4;
     if (b->has_m) {
-        b->lds = std::max(b->lds, (size_t)(16 * 17 + 1) * 4);
-        b->lds = std::max(b->lds, (size_t)4 * b->zs_rank * 16 * 4);
+        b->lds = std::max(b->lds, (size_t)4 * 4);                    // X packing: one maximum per wave
+        b->lds = std::max(b->lds, (size_t)4 * b->zs_rank * 16 * 4);  // z packing: rank x 16 values per wave
     }
     b->lds = std::max<size_t>((b->lds + 15) / 16 * 16, 16);
     // take the references now: release_batch drops one per member

@@ -1263,6 +1263,9 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     h->flags = opts->flags;
     for (int64_t b = 0; b < nb; ++b) h->max_rank = std::max(h->max_rank, blocks[b].rank);
     {
+        // work estimates for the batched scheduler; kLatencyBytes prices one
+        // round trip of a latency-bound reduction item in bytes of streaming
+        constexpr float kLatencyBytes = 4096.0f;
         const float esz = opts->storage == HMAT_STORE_FP32 ? 4.0f : 2.0f;
         if (h->mr) {
             for (const hmat::MRChunk &c : hpm.chunks) {
@@ -1276,8 +1279,10 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
             }
             for (const hmat::MRTile &tl : hpm.tiles)
                 h->cost_tgt.push_back((float)((int64_t)hpm.chunks[tl.chunk].nsteps * tl.nm * 1024));
-            for (const hmat::MRZItem &z : hpm.zitems)  // partials read, B fragments written (one n-tile)
-                h->cost_z1.push_back((float)z.nu * z.rank * 64 + (float)z.rank * 64 * 2);
+            // partials read and B fragments written (one n-tile), plus a latency term: these small
+            // items are bound by round trips, not bytes
+            for (const hmat::MRZItem &z : hpm.zitems)
+                h->cost_z1.push_back((float)z.nu * z.rank * 64 + (float)z.rank * 64 * 2 + kLatencyBytes);
         } else {
             for (const ChunkMeta &c : hp.chunks) {
                 h->chunk_rows.push_back(c.rows);
@@ -1288,8 +1293,8 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 const int64_t nvec = (hp.chunks[vt.chunk].rows + hp.vw - 1) / hp.vw;
                 h->cost_src.push_back((float)nvec * hmat::kWave * hp.vw * esz);
             }
-            for (const ZItem &z : hp.z1) h->cost_z1.push_back((float)(z.nchunks + 1) * z.rank * 4);
-            for (const ZItem2 &z : hp.z2) h->cost_z2.push_back((float)(z.nslices + 1) * z.rank * 4);
+            for (const ZItem &z : hp.z1) h->cost_z1.push_back((float)(z.nchunks + 1) * z.rank * 4 + kLatencyBytes);
+            for (const ZItem2 &z : hp.z2) h->cost_z2.push_back((float)(z.nslices + 1) * z.rank * 4 + kLatencyBytes);
         }
     }
     hmat_info &in = h->info;

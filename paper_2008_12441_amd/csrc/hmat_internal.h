@@ -266,7 +266,7 @@ struct BItem {
     int32_t dep;          // counter that must reach `need` before the item starts, -1 for none
     int32_t need;
     int32_t done;         // counter incremented when the item has completed, -1 for none
-    int32_t pad_;
+    int32_t lanes;        // reduction items: lanes per unit (a power of two <= 64)
 };
 
 struct BMember {

@@ -378,53 +378,83 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
 
 // ---------------------------------------------------------------------------
 // X -> B fragments for one (chunk, n-tile of 16 columns), by a workgroup of
-// 256 threads; red (16 x 17 floats) and sig (1 float) are LDS scratch.
+// 256 threads; red (4 floats of LDS) takes the per-wave maxima. Lane l of
+// wave w reads rows 8 (l / 16) .. of K-blocks w, w + 4, ... of column
+// 16 nt + l % 16, which is where they sit in the fragment. The first four
+// K-blocks of every wave stay in registers between the amax and the split, so
+// a chunk of up to 16 K-blocks (512 rows in FP16) reads X once; the rest of a
+// longer chunk is read a second time.
 // ---------------------------------------------------------------------------
 template <int STORE>
 __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx, int k,
-                                float (*red)[17], float *sig) {
+                                float *red) {
     using F = MR<STORE>;
     constexpr int VW = F::VW;
     constexpr int KB = F::KB;
+    constexpr int R = 4;  // K-blocks per wave held in registers
     const MRChunk ch = cload(p.chunks, c);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (F::SCALED) {
-        // 16 threads per column read 16 consecutive rows at a time
-        const int cc = tid >> 4, r0 = tid & 15;
-        const int n = nt * 16 + cc;
-        float m = 0.0f;
-        if (n < k) {
-            const float *col = x + (int64_t)n * ldx + ch.row_begin;
-            for (int i = r0; i < ch.rows; i += 16) m = fmaxf(m, fabsf(col[i]));
-        }
-        red[cc][r0] = m;
-        __syncthreads();
-        if (tid == 0) {
-            float a = 0.0f;
-            for (int i = 0; i < 16; ++i)
-                for (int j = 0; j < 16; ++j) a = fmaxf(a, red[i][j]);
-            const float s = col_scale(a);
-            sig[0] = s;
-            p.sx[(int64_t)c * p.ntmax + nt] = s;
-        }
-        __syncthreads();
-    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = nt * 16 + (lane & 15);
-    const float inv = F::SCALED ? 1.0f / sig[0] : 1.0f;
     const float *col = x + (int64_t)n * ldx;
-    for (int kb = wave; kb < ch.nkb; kb += 4) {
-        // the leaf holding this K-block (leaves start on K-block boundaries)
+    // the leaf holding K-block kb (leaves start on K-block boundaries)
+    auto leaf_of = [&](int kb) {
         int lf = 0;
         while (lf + 1 < ch.nleaf && cload(p.leaves, ch.leaf_base + lf + 1).kb0 <= kb) ++lf;
-        const MRLeaf L = cload(p.leaves, ch.leaf_base + lf);
+        return cload(p.leaves, ch.leaf_base + lf);
+    };
+    auto gather = [&](int kb, float (&v)[VW]) {  // zero past the leaf's rows and past column k
+        const MRLeaf L = leaf_of(kb);
         const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
-        float v[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int o = off0 + e;
-            v[e] = (n < k && o < L.rows) ? col[L.row_begin + o] * inv : 0.0f;
+            v[e] = (n < k && o < L.rows) ? col[L.row_begin + o] : 0.0f;
         }
-        F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, v);
+    };
+    auto store = [&](int kb, const float (&v)[VW], float inv) {
+        float t[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) t[e] = v[e] * inv;
+        F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, t);
+    };
+    float v[R][VW];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (wave + 4 * r < ch.nkb) {
+            gather(wave + 4 * r, v[r]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[r][e] = 0.0f;
+        }
+    }
+    float inv = 1.0f;
+    if (F::SCALED) {
+        float m = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) m = fmaxf(m, fabsf(v[r][e]));
+        for (int kb = wave + 4 * R; kb < ch.nkb; kb += 4) {
+            float t[VW];
+            gather(kb, t);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) m = fmaxf(m, fabsf(t[e]));
+        }
+        m = wave_max(m);
+        if (lane == 0) red[wave] = m;
+        __syncthreads();
+        const float s = col_scale(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+        if (tid == 0) p.sx[(int64_t)c * p.ntmax + nt] = s;
+        inv = 1.0f / s;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (wave + 4 * r < ch.nkb) store(wave + 4 * r, v[r], inv);
+    for (int kb = wave + 4 * R; kb < ch.nkb; kb += 4) {
+        float t[VW];
+        gather(kb, t);
+        store(kb, t, inv);
     }
 }
 
@@ -504,22 +534,32 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     const int n = nt * 16 + nn;
     const int64_t ustride = (int64_t)64 * ncol;
     float amax = 0.0f;
-    for (int j = g; j < z.rank; j += 4) {
-        const int col = z.vcol + j;
-        const int64_t u0 = z.ubase + (int64_t)(col >> 6) * z.nu;
-        const float *src = p.part + u0 * ustride + (int64_t)(col & 63) * ncol + n;
-        float a0 = 0.0f, a1 = 0.0f;
-        int i = 0;
-        for (; i + 2 <= z.nu; i += 2) {
-            a0 += src[(int64_t)i * ustride];
-            a1 += src[(int64_t)(i + 1) * ustride];
+    // lane group g sums columns g, g + 4, g + 8, ... of the block; four of them
+    // at a time, so that four independent loads are in flight per unit (the
+    // addresses of columns past the rank are clamped, their sums dropped)
+    for (int j0 = g; j0 < z.rank; j0 += 16) {
+        const float *src[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + 4 * q < z.rank ? j0 + 4 * q : z.rank - 1;
+            const int col = z.vcol + j;
+            src[q] = p.part + (z.ubase + (int64_t)(col >> 6) * z.nu) * ustride + (int64_t)(col & 63) * ncol + n;
         }
-        if (i < z.nu) a0 += src[(int64_t)i * ustride];
-        float zsc = z.scale;
-        if constexpr (F::FP8) zsc = p.zcol[z.col_off + j];  // s_j of U times s_j of V
-        const float s = (a0 + a1) * zsc;
-        zs[j][nn] = s;
-        amax = fmaxf(amax, fabsf(s));
+        float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < z.nu; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] += src[q][(int64_t)i * ustride];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + 4 * q;
+            if (j < z.rank) {
+                float zsc = z.scale;
+                if constexpr (F::FP8) zsc = p.zcol[z.col_off + j];  // s_j of U times s_j of V
+                const float sj = a[q] * zsc;
+                zs[j][nn] = sj;
+                amax = fmaxf(amax, fabsf(sj));
+            }
+        }
     }
     amax = wave_max(amax);
     const float sig = F::SCALED ? col_scale(amax) : 1.0f;

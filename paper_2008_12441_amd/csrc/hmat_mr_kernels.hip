@@ -28,10 +28,9 @@ __device__ inline int wave_id_xcd(int waves_per_block) {
 
 template <int STORE>
 __global__ __launch_bounds__(256) void k_xpack(DevPlanMR p, const float *__restrict__ x, int64_t ldx, int k) {
-    __shared__ float red[16][17];
-    __shared__ float sig[1];
+    __shared__ float red[4];
     const int nt_used = (k + 15) / 16;
-    mr_xpack<STORE>(p, blockIdx.x / nt_used, blockIdx.x % nt_used, x, ldx, k, red, sig);
+    mr_xpack<STORE>(p, blockIdx.x / nt_used, blockIdx.x % nt_used, x, ldx, k, red);
 }
 
 template <int STORE, int NT>

@@ -164,6 +164,54 @@ __device__ inline void sv_z2(const DevPlan &p, int w, int lane) {
     }
 }
 
+// The two reduction stages over a run of items [first, first + count), for
+// ranks well below 64: a wave takes 64 / R items at a time, lane l working
+// on item l / R and rank index l % R (R a power of two; an item of larger
+// rank loops). Each item's sums are the ones sv_z1 / sv_z2 form, in the same
+// order, so the results are bitwise the same.
+template <class Acc>
+__device__ inline void sv_z1_packed(const DevPlan &p, int first, int count, int R, int wave, int lane) {
+    const int per = 64 / R, sub = lane / R, kk = lane % R;
+    Acc *zg = static_cast<Acc *>(p.zg);
+    for (int j = wave * per + sub; j < count; j += 4 * per) {
+        const ZItem it = p.z1[first + j];
+        const int32_t *pb = p.pbase + it.chunk0;
+        for (int k = kk; k < it.rank; k += R) {
+            Acc a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const Acc *src = static_cast<const Acc *>(p.part) + it.vcol + k;
+            int c = 0;
+            for (; c + 8 <= it.nchunks; c += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += src[pb[c + u]];
+            }
+            for (; c < it.nchunks; ++c) a[0] += src[pb[c]];
+            const Acc s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+            zg[it.dst + k] = s * (Acc)it.scale;
+        }
+    }
+}
+
+template <class Acc>
+__device__ inline void sv_z2_packed(const DevPlan &p, int first, int count, int R, int wave, int lane) {
+    const int per = 64 / R, sub = lane / R, kk = lane % R;
+    Acc *zg = static_cast<Acc *>(p.zg);
+    for (int j = wave * per + sub; j < count; j += 4 * per) {
+        const ZItem2 it = p.z2[first + j];
+        for (int k = kk; k < it.rank; k += R) {
+            Acc a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const Acc *src = zg + it.src + k;
+            int c = 0;
+            for (; c + 8 <= it.nslices; c += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += src[(c + u) * it.rank];
+            }
+            for (; c < it.nslices; ++c) a[0] += src[c * it.rank];
+            const Acc s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+            zg[it.dst + k] = s * (Acc)it.scale;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // U-phase + dense near field + output for one chunk, by a workgroup of 256
 // threads. The chunk's vector operand (its ancestors' z segments, then x over
