@@ -11,6 +11,11 @@ workload number).
   c3  3D, 64^3 grid (N = 262144), 1/r kernel, rank 64, randomized SVD, 64 RHS
   c4  256 independent sub-grid H-matrices (see ``batch_problems``)
   c5  3D, 128^3 grid (N = 2^21), 1/r kernel, rank 32, randomized SVD, 128 RHS
+  s2  2D, 1024 x 1024 grid (N = 2^20), standard admissibility, rank 4, random
+      fills (the paper's two-dimensional experiments: random factors, r = 4), 1 RHS
+  s3  3D, 64^3 grid (N = 262144), standard admissibility, rank 4, random fills, 1 RHS
+
+Weak admissibility unless stated otherwise.
 """
 from __future__ import annotations
 
@@ -33,6 +38,7 @@ class Workload:
     method: str
     nrhs: int
     rhs_seed: int
+    admissibility: str = "weak"
 
     @property
     def n(self) -> int:
@@ -41,7 +47,7 @@ class Workload:
     def describe(self) -> str:
         kern = "-log|x-y|/(2pi)" if self.kind == "log" else "1/(4pi|x-y|)"
         return (f"{self.d}D uniform grid {self.n_axis}^{self.d} (N={self.n}), leaf 64, "
-                f"kernel {kern} (diag 1), weak admissibility, rank {self.rank} "
+                f"kernel {kern} (diag 1), {self.admissibility} admissibility, rank {self.rank} "
                 f"({self.method}), {self.nrhs} RHS")
 
 
@@ -50,6 +56,8 @@ WORKLOADS = {
     "c2": Workload("c2", 2, 1024, "log", 32, "rsvd", 1, 1002),
     "c3": Workload("c3", 3, 64, "inv", 64, "rsvd", 64, 1003),
     "c5": Workload("c5", 3, 128, "inv", 32, "rsvd", 128, 1005),
+    "s2": Workload("s2", 2, 1024, "log", 4, "random", 1, 1006, "standard"),
+    "s3": Workload("s3", 3, 64, "inv", 4, "random", 1, 1007, "standard"),
 }
 
 
@@ -63,7 +71,7 @@ def build_workload(name: str, *, method: str | None = None, device=None, seed: i
     n_axis = n_axis or w.n_axis
     tree = uniform_tree(w.d, n_axis)
     data = make_hmatrix(tree, rank or w.rank, kind=w.kind, method=method or w.method,
-                        seed=seed, device=device)
+                        seed=seed, device=device, admissibility=w.admissibility)
     x = make_rhs(tree.n, w.nrhs, w.rhs_seed)
     return data, x
 

@@ -237,8 +237,10 @@ def _random_fill_torch(pool, blocks, off_a, off_b, sz, seed, device):
 
 def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str = "svd",
                  seed: int = 0, oversample: int = 10, device=None, dedupe: bool = True,
-                 gpu_min_entries: int = 1 << 24) -> HMatrixData:
+                 gpu_min_entries: int = 1 << 24, admissibility: str = "weak") -> HMatrixData:
     """Build the canonical FP32 factor set for the H-matrix of ``tree``.
+
+    ``admissibility`` ("weak" or "standard") selects the block structure.
 
     method:
       ``svd``      exact truncated SVD of every low-rank block;
@@ -263,7 +265,7 @@ def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str
     """
     if method == "fullrank":
         rank = 1 << 30
-    blocks = enumerate_blocks(tree, rank)
+    blocks = enumerate_blocks(tree, rank, admissibility)
     off_a, off_b, total = _layout(tree, blocks)
     pool = np.empty(total, dtype=np.float32)
     sz = tree.end - tree.begin
@@ -274,16 +276,24 @@ def make_hmatrix(tree: ClusterTree, rank: int, *, kind: str = "log", method: str
     if method == "random":
         rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xD0]))
         rng.standard_normal(size=total, dtype=np.float32, out=pool)
-        for b in range(len(blocks)):
-            t, s, r = int(blocks.target[b]), int(blocks.source[b]), int(blocks.rank[b])
-            m, n = int(sz[t]), int(sz[s])
-            o = int(off_a[b])
-            if r == 0:
-                pool[o:o + m * n] *= np.float32(1.0 / math.sqrt(n))
-            else:
-                pool[o:o + m * r] *= np.float32(1.0 / math.sqrt(r))
-                ob = int(off_b[b])
-                pool[ob:ob + n * r] *= np.float32(1.0 / math.sqrt(n))
+        # per-block factors as FP32 scalars, applied segment by segment (U, then V, of a block)
+        m = sz[blocks.target].astype(np.int64)
+        n = sz[blocks.source].astype(np.int64)
+        r = blocks.rank.astype(np.int64)
+        lr = r > 0
+        starts = np.concatenate([off_a, off_b[lr]])
+        lens = np.concatenate([np.where(lr, m * r, m * n), n[lr] * r[lr]])
+        fac = np.concatenate([np.where(lr, 1.0 / np.sqrt(np.maximum(r, 1)), 1.0 / np.sqrt(n)),
+                              1.0 / np.sqrt(n[lr])]).astype(np.float32)
+        order = np.argsort(starts, kind="stable")
+        starts, lens, fac = starts[order], lens[order], fac[order]
+        step = 1 << 24
+        i = 0
+        while i < len(starts):  # runs of whole segments, about `step` entries at a time
+            j = max(int(np.searchsorted(starts, starts[i] + step, side="right")), i + 1)
+            o0, o1 = int(starts[i]), int(starts[j - 1] + lens[j - 1])
+            pool[o0:o1] *= np.repeat(fac[i:j], lens[i:j])
+            i = j
         return HMatrixData(tree, blocks, pool, off_a, off_b, kind, method)
 
     if method not in ("svd", "rsvd", "fullrank"):

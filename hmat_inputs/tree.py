@@ -1,4 +1,4 @@
-"""Geometry, cluster tree and block structure of a weak-admissibility H-matrix.
+"""Geometry, cluster tree and block structure of an H-matrix (weak or standard admissibility).
 
 This module only builds *inputs*: point sets on a grid, the domain tree
 (Sec. 2, Def. "Domain tree"), and the list of dense and low-rank blocks that
@@ -199,7 +199,16 @@ class BlockList:
         return len(self.target)
 
 
-def enumerate_blocks(tree: ClusterTree, rank: int) -> BlockList:
+def enumerate_blocks(tree: ClusterTree, rank: int, admissibility: str = "weak") -> BlockList:
+    """Blocks of Def. 2.3 under the weak or the standard admissibility condition."""
+    if admissibility == "weak":
+        return _enumerate_weak(tree, rank)
+    if admissibility == "standard":
+        return enumerate_blocks_standard(tree, rank)
+    raise ValueError(f"unknown admissibility condition {admissibility!r}")
+
+
+def _enumerate_weak(tree: ClusterTree, rank: int) -> BlockList:
     """Blocks of Def. 2.3 under weak admissibility, checked in the definition's order.
 
     For every child pair (ct, cs) of a recursion pair: (1) if either child is a
@@ -228,6 +237,68 @@ def enumerate_blocks(tree: ClusterTree, rank: int) -> BlockList:
                 else:
                     stack.append(ct)
     return BlockList(np.asarray(tgt, np.int32), np.asarray(src, np.int32), np.asarray(rk, np.int32))
+
+
+def standard_admissible(tree: ClusterTree, t, s, rho2=None) -> np.ndarray:
+    """Sec. 2, Def. "Standard admissibility condition": min(diam t, diam s) <= rho dist(t, s).
+
+    A box is the closed region [lo, lo + shape] / n_full of the cells it owns
+    (its points are the cell centres). rho = sqrt(d), the paper's choice, unless
+    ``rho2`` (rho squared) is given. The comparison is exact: squared lengths in
+    integer units of 1 / lcm(n_full).
+    """
+    t = np.asarray(t, np.int64)
+    s = np.asarray(s, np.int64)
+    d = tree.d
+    rho2 = d if rho2 is None else rho2
+    m = math.lcm(*[int(v) for v in tree.n_full])
+    unit = np.asarray([m // int(v) for v in tree.n_full], np.int64)
+    lo_t, lo_s = tree.lo[t] * unit, tree.lo[s] * unit
+    hi_t, hi_s = lo_t + tree.shape[t] * unit, lo_s + tree.shape[s] * unit
+    diam2_t = np.sum((hi_t - lo_t) ** 2, axis=-1)
+    diam2_s = np.sum((hi_s - lo_s) ** 2, axis=-1)
+    gap = np.maximum(np.maximum(lo_s - hi_t, lo_t - hi_s), 0)
+    dist2 = np.sum(gap ** 2, axis=-1)
+    return np.minimum(diam2_t, diam2_s) <= rho2 * dist2
+
+
+def enumerate_blocks_standard(tree: ClusterTree, rank: int, rho2=None) -> BlockList:
+    """Blocks of Def. 2.3 under standard admissibility, in the definition's order.
+
+    Recursion pairs are visited level by level from (root, root); for each, its
+    child pairs (ct, cs) in child order: (1) a leaf child makes the block dense;
+    else (2) an admissible pair is low-rank; else (3) the pair recurses. On an
+    ideal domain this gives low-rank blocks between boxes whose parents are
+    neighbours but which are not neighbours themselves, and dense blocks between
+    every leaf and the leaves of its parent's neighbours.
+    """
+    if tree.is_leaf(0):
+        return BlockList(np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros(1, np.int32))
+    nn = tree.num_nodes
+    width = max(len(c) for c in tree.children)
+    kids = np.full((nn, width), -1, np.int64)
+    for a, c in enumerate(tree.children):
+        kids[a, :len(c)] = c
+    size = (tree.end - tree.begin).astype(np.int64)
+    leaf = np.asarray([len(c) == 0 for c in tree.children])
+    tgt, src, rk = [], [], []
+    pairs = np.zeros((1, 2), np.int64)
+    while len(pairs):
+        ct = np.repeat(kids[pairs[:, 0]], width, axis=1).reshape(-1)
+        cs = np.tile(kids[pairs[:, 1]], (1, width)).reshape(-1)
+        ok = (ct >= 0) & (cs >= 0)
+        ct, cs = ct[ok], cs[ok]
+        is_leaf = leaf[ct] | leaf[cs]
+        adm = np.zeros(len(ct), bool)
+        adm[~is_leaf] = standard_admissible(tree, ct[~is_leaf], cs[~is_leaf], rho2)
+        block = is_leaf | adm
+        tgt.append(ct[block])
+        src.append(cs[block])
+        rk.append(np.where(is_leaf[block], 0,
+                           np.minimum(np.minimum(size[ct[block]], size[cs[block]]), rank)))
+        pairs = np.stack([ct[~block], cs[~block]], axis=1)
+    return BlockList(np.concatenate(tgt).astype(np.int32), np.concatenate(src).astype(np.int32),
+                     np.concatenate(rk).astype(np.int32))
 
 
 def stored_elements(tree: ClusterTree, blocks: BlockList) -> int:

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -285,12 +286,22 @@ hmat_status analyse_tree(const hmat_tree_desc *td, Tree &t) {
     return HMAT_OK;
 }
 
+// The block structure of Def. 2.3: starting from the pair (root, root),
+// every child pair of a recursion pair is a dense block (leaf pairs), a
+// low-rank block (admissible pairs) or a recursion pair itself. The
+// admissibility condition is the caller's: any block set of this shape is
+// accepted, so weak admissibility (low-rank blocks between distinct siblings)
+// and standard admissibility (low-rank blocks between boxes whose parents are
+// neighbours, dense blocks between neighbouring parents' leaves) both are.
 struct Structure {
-    std::vector<int64_t> slot_base;  // per node: offset into slot (k^2 pairs of its children)
-    std::vector<int64_t> slot;       // block index per ordered child pair, -1 if absent
-    int64_t block_of(const Tree &t, int32_t a, int32_t b) const {
-        const int32_t p = t.parent[a];
-        return slot[slot_base[p] + (int64_t)t.child_pos[a] * t.nkids(p) + t.child_pos[b]];
+    std::unordered_map<uint64_t, int64_t> index;             // (target, source) -> block
+    std::vector<std::vector<int64_t>> by_target, by_source;  // low-rank blocks of a node, by the other node's first row
+    std::vector<std::vector<int32_t>> dense_src;             // per node at depth L-1: the source leaves of its
+                                                             // children's dense blocks, by first row
+    static uint64_t key(int32_t a, int32_t b) { return (uint64_t)(uint32_t)a << 32 | (uint32_t)b; }
+    int64_t find(int32_t a, int32_t b) const {
+        const auto it = index.find(key(a, b));
+        return it == index.end() ? -1 : it->second;
     }
 };
 
@@ -319,43 +330,81 @@ hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb
             return fail(HMAT_ERR_BAD_BLOCKS, "a tree whose root is a leaf takes exactly one dense block (0, 0)");
         return HMAT_OK;
     }
-    st.slot_base.assign(nn + 1, 0);
-    for (int32_t p = 0; p < nn; ++p)
-        st.slot_base[p + 1] = st.slot_base[p] + (int64_t)t.nkids(p) * t.nkids(p);
-    st.slot.assign(st.slot_base[nn], -1);
+    auto name = [&](int64_t b) {
+        return "block " + std::to_string(b) + " (" + std::to_string(bl[b].target) + ", " +
+               std::to_string(bl[b].source) + ")";
+    };
+    st.index.reserve((size_t)nb * 2);
     for (int64_t b = 0; b < nb; ++b) {
         const hmat_block_desc &d = bl[b];
-        const std::string id = "block " + std::to_string(b) + " (" + std::to_string(d.target) + ", " +
-                               std::to_string(d.source) + ")";
         if (d.target == 0 || d.source == 0)
-            return fail(HMAT_ERR_BAD_BLOCKS, id + ": the root pair is never a block of Def. 2.3");
-        const int32_t p = t.parent[d.target];
-        if (t.parent[d.source] != p)
-            return fail(HMAT_ERR_UNSUPPORTED, id + ": blocks between non-siblings (standard admissibility) are not supported");
-        if (t.depth[p] == t.L - 1) {
-            if (d.rank != 0)
-                return fail(HMAT_ERR_UNSUPPORTED, id + ": low-rank blocks between leaves are not supported (Def. 2.3 makes them dense)");
-        } else {
-            if (d.target == d.source)
-                return fail(HMAT_ERR_BAD_BLOCKS, id + ": (c, c) above the leaves is a recursion pair, not a block");
-            if (d.rank == 0)
-                return fail(HMAT_ERR_UNSUPPORTED, id + ": dense blocks between non-leaf siblings are not supported");
-        }
-        int64_t &s = st.slot[st.slot_base[p] + (int64_t)t.child_pos[d.target] * t.nkids(p) + t.child_pos[d.source]];
-        if (s >= 0) return fail(HMAT_ERR_BAD_BLOCKS, id + ": duplicate block");
-        s = b;
+            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": the root pair is never a block of Def. 2.3");
+        if (!st.index.emplace(Structure::key(d.target, d.source), b).second)
+            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": duplicate block");
     }
+    // walk the recursion pairs level by level; every child pair must be a block or recurse
+    std::vector<uint8_t> seen(nb, 0);
+    std::vector<std::vector<int32_t>> partners(nn);
+    std::vector<std::pair<int32_t, int32_t>> frontier{{0, 0}}, next;
+    while (!frontier.empty()) {
+        next.clear();
+        for (const auto &pq : frontier) {
+            const int32_t p = pq.first, q = pq.second;
+            if (t.depth[p] == t.L - 1) partners[p].push_back(q);
+            for (int32_t i = 0; i < t.nkids(p); ++i)
+                for (int32_t j = 0; j < t.nkids(q); ++j) {
+                    const int32_t ct = t.kid(p, i), cs = t.kid(q, j);
+                    const int64_t b = st.find(ct, cs);
+                    const bool leaves = t.leaf(ct);  // all leaves share one depth, and so do ct and cs
+                    if (b < 0) {
+                        if (leaves)
+                            return fail(HMAT_ERR_BAD_BLOCKS, "missing block (" + std::to_string(ct) + ", " +
+                                                                 std::to_string(cs) + ")");
+                        next.emplace_back(ct, cs);
+                        continue;
+                    }
+                    seen[b] = 1;
+                    if (leaves) {
+                        if (bl[b].rank != 0)
+                            return fail(HMAT_ERR_UNSUPPORTED,
+                                        name(b) + ": low-rank blocks between leaves are not supported (Def. 2.3 "
+                                                  "makes them dense)");
+                    } else {
+                        if (ct == cs)
+                            return fail(HMAT_ERR_BAD_BLOCKS,
+                                        name(b) + ": (c, c) above the leaves is a recursion pair, not a block");
+                        if (bl[b].rank == 0)
+                            return fail(HMAT_ERR_UNSUPPORTED,
+                                        name(b) + ": dense blocks between non-leaf boxes are not supported");
+                    }
+                }
+        }
+        frontier.swap(next);
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        if (!seen[b])
+            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": not a child pair of a recursion pair (it overlaps "
+                                                       "another block or pairs boxes of different depths)");
+    // low-rank blocks per node, and the dense sources of every depth-(L-1) node
+    st.by_target.assign(nn, {});
+    st.by_source.assign(nn, {});
+    for (int64_t b = 0; b < nb; ++b)
+        if (bl[b].rank > 0) {
+            st.by_target[bl[b].target].push_back(b);
+            st.by_source[bl[b].source].push_back(b);
+        }
+    for (int32_t a = 0; a < nn; ++a) {
+        std::sort(st.by_target[a].begin(), st.by_target[a].end(),
+                  [&](int64_t x, int64_t y) { return t.begin[bl[x].source] < t.begin[bl[y].source]; });
+        std::sort(st.by_source[a].begin(), st.by_source[a].end(),
+                  [&](int64_t x, int64_t y) { return t.begin[bl[x].target] < t.begin[bl[y].target]; });
+    }
+    st.dense_src.assign(nn, {});
     for (int32_t p = 0; p < nn; ++p) {
-        const int32_t k = t.nkids(p);
-        if (k == 0) continue;
-        const bool leaf_parent = t.depth[p] == t.L - 1;
-        for (int32_t i = 0; i < k; ++i)
-            for (int32_t j = 0; j < k; ++j) {
-                if (!leaf_parent && i == j) continue;
-                if (st.slot[st.slot_base[p] + (int64_t)i * k + j] < 0)
-                    return fail(HMAT_ERR_BAD_BLOCKS, "missing block (" + std::to_string(t.kid(p, i)) + ", " +
-                                                         std::to_string(t.kid(p, j)) + ")");
-            }
+        auto &q = partners[p];
+        std::sort(q.begin(), q.end(), [&](int32_t x, int32_t y) { return t.begin[x] < t.begin[y]; });
+        for (int32_t r : q)
+            for (int32_t j = 0; j < t.nkids(r); ++j) st.dense_src[p].push_back(t.kid(r, j));
     }
     return HMAT_OK;
 }
@@ -386,6 +435,15 @@ struct HostPlan {
 };
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// The leaves below a chunk node: its children, or the node itself when the root is a leaf.
+std::vector<int32_t> chunk_leaves(const Tree &t, int32_t node) {
+    std::vector<int32_t> v;
+    if (t.L == 0) v.push_back(node);
+    else
+        for (int32_t j = 0; j < t.nkids(node); ++j) v.push_back(t.kid(node, j));
+    return v;
+}
 
 hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc *bl, int64_t nb,
                        int32_t storage, int32_t acc_bytes, HostPlan &hp) {
@@ -441,7 +499,7 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
         if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
     }
 
-    // z layout: per non-leaf node t at depth 1..L-1, the z vectors of its sibling blocks
+    // z layout: per non-leaf node t at depth 1..L-1, the z vectors of its low-rank blocks (t, s)
     hp.zoff.assign(t.num_nodes, 0);
     hp.zlen.assign(t.num_nodes, 0);
     hp.zdst.assign(nb, -1);
@@ -449,13 +507,9 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
     int64_t zcur = 0;
     for (int32_t a = 1; a < t.num_nodes && L >= 2; ++a) {
         if (t.depth[a] < 1 || t.depth[a] > L - 1) continue;
-        const int32_t p = t.parent[a];
         hp.zoff[a] = (int32_t)zcur;
         int32_t off = 0;
-        for (int32_t j = 0; j < t.nkids(p); ++j) {
-            const int32_t s = t.kid(p, j);
-            if (s == a) continue;
-            const int64_t b = st.block_of(t, a, s);
+        for (const int64_t b : st.by_target[a]) {
             hp.zdst[b] = (int32_t)(zcur + off);
             off += rank_of(b);
         }
@@ -478,11 +532,7 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
         int32_t wv = 0;
         for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
             const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
-            const int32_t p = t.parent[a];
-            for (int32_t j = 0; j < t.nkids(p); ++j) {
-                const int32_t tt = t.kid(p, j);
-                if (tt == a) continue;
-                const int64_t b = st.block_of(t, tt, a);
+            for (const int64_t b : st.by_source[a]) {
                 if (hp.vcol[b] < 0) hp.vcol[b] = wv;
                 else if (hp.vcol[b] != wv)
                     return fail(HMAT_ERR_UNSUPPORTED, "inconsistent source column layout");
@@ -510,31 +560,29 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
             wlr += hp.zlen[a];
         }
         m.nq_lr = (wlr + vw - 1) / vw;
-        // dense part: one segment per leaf (the chunk's children, or the root itself)
+        // dense part: one segment per source leaf of the chunk's dense blocks, then
+        // (for the row -> target leaf lookup) one per target leaf, the chunk's children
         m.dseg_base = (int32_t)hp.dsegs.size();
-        std::vector<int32_t> leaves;
-        if (L == 0) leaves.push_back(node);
-        else
-            for (int32_t j = 0; j < t.nkids(node); ++j) leaves.push_back(t.kid(node, j));
-        m.nleaf = (int32_t)leaves.size();
+        const std::vector<int32_t> tleaves = chunk_leaves(t, node);
+        const std::vector<int32_t> &sleaves = L == 0 ? tleaves : st.dense_src[node];
+        m.nleaf = (int32_t)sleaves.size();
+        m.ntleaf = (int32_t)tleaves.size();
         int32_t nq = m.nq_lr;
-        for (int32_t lf : leaves) {
-            DSeg ds;
-            ds.row_begin = (int32_t)t.begin[lf];
-            ds.rows = (int32_t)t.size(lf);
-            ds.nq = (ds.rows + vw - 1) / vw;
-            ds.pad_ = 0;
-            nq += ds.nq;
-            hp.dsegs.push_back(ds);
-            hp.max_leaf_rows = std::max(hp.max_leaf_rows, ds.rows);
-        }
+        for (int32_t pass = 0; pass < 2; ++pass)
+            for (int32_t lf : pass == 0 ? sleaves : tleaves) {
+                DSeg ds;
+                ds.row_begin = (int32_t)t.begin[lf];
+                ds.rows = (int32_t)t.size(lf);
+                ds.nq = (ds.rows + vw - 1) / vw;
+                ds.pad_ = 0;
+                if (pass == 0) nq += ds.nq;
+                hp.dsegs.push_back(ds);
+                hp.max_leaf_rows = std::max(hp.max_leaf_rows, ds.rows);
+            }
         m.nq = nq;
         m.dscale_base = (int32_t)hp.dscale.size();
-        for (int32_t it = 0; it < m.nleaf; ++it)
-            for (int32_t is = 0; is < m.nleaf; ++is) {
-                int64_t b = (L == 0) ? 0 : st.block_of(t, leaves[it], leaves[is]);
-                hp.dscale.push_back(hp.sD[b]);
-            }
+        for (int32_t lt : tleaves)
+            for (int32_t ls : sleaves) hp.dscale.push_back(hp.sD[L == 0 ? 0 : st.find(lt, ls)]);
         m.ud_off = ud_cur;
         const int32_t ntile = (m.rows + hmat::kWave - 1) / hmat::kWave;
         ud_cur += (int64_t)ntile * nq * hmat::kWave * vw;
@@ -597,12 +645,8 @@ void fill_v(const Tree &t, const Structure &st, const hmat_block_desc *bl, const
         int32_t col = 0;
         for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
             const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
-            const int32_t p = t.parent[a];
             const int64_t roff = m.row_begin - t.begin[a];
-            for (int32_t j = 0; j < t.nkids(p); ++j) {
-                const int32_t tt = t.kid(p, j);
-                if (tt == a) continue;
-                const int64_t b = st.block_of(t, tt, a);
+            for (const int64_t b : st.by_source[a]) {
                 const hmat_block_desc &d = bl[b];
                 const float inv = 1.0f / hp.sV[b];
                 for (int32_t k = 0; k < d.rank; ++k, ++col) {
@@ -641,12 +685,8 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
         int32_t col = 0;
         for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
             const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
-            const int32_t p = t.parent[a];
             const int64_t roff = m.row_begin - t.begin[a];
-            for (int32_t j = 0; j < t.nkids(p); ++j) {
-                const int32_t s = t.kid(p, j);
-                if (s == a) continue;
-                const int64_t b = st.block_of(t, a, s);
+            for (const int64_t b : st.by_target[a]) {
                 const hmat_block_desc &d = bl[b];
                 const float inv = 1.0f / hp.sU[b];
                 for (int32_t k = 0; k < d.rank; ++k, ++col) {
@@ -661,24 +701,23 @@ void fill_ud(const Tree &t, const Structure &st, const hmat_block_desc *bl, cons
         }
         for (; col < m.nq_lr * vw; ++col)
             for (int32_t i = 0; i < prow; ++i) put(i, col, T(0));
-        // dense part, grouped by source leaf
+        // dense part, grouped by source leaf; the target leaf of a row selects the block
+        const std::vector<int32_t> tleaves = chunk_leaves(t, hp.chunk_node[c]);
+        const std::vector<int32_t> &sleaves = L == 0 ? tleaves : st.dense_src[hp.chunk_node[c]];
+        const DSeg *tsegs = hp.dsegs.data() + m.dseg_base + m.nleaf;
         int32_t qcol = m.nq_lr * vw;
         for (int32_t is = 0; is < m.nleaf; ++is) {
             const DSeg &sseg = hp.dsegs[m.dseg_base + is];
+            std::vector<int64_t> blk(m.ntleaf);
+            for (int32_t it = 0; it < m.ntleaf; ++it) blk[it] = L == 0 ? 0 : st.find(tleaves[it], sleaves[is]);
             for (int32_t jj = 0; jj < sseg.nq * vw; ++jj, ++qcol) {
                 for (int32_t it = 0, i = 0; i < prow; ++i) {
                     float v = 0.0f;
                     float inv = 1.0f;
                     if (i < m.rows && jj < sseg.rows) {
-                        while (it + 1 < m.nleaf &&
-                               m.row_begin + i >= hp.dsegs[m.dseg_base + it + 1].row_begin)
-                            ++it;
-                        const DSeg &tseg = hp.dsegs[m.dseg_base + it];
-                        int64_t b = 0;
-                        if (L > 0) {
-                            const int32_t node = hp.chunk_node[c];
-                            b = st.block_of(t, t.kid(node, it), t.kid(node, is));
-                        }
+                        while (it + 1 < m.ntleaf && m.row_begin + i >= tsegs[it + 1].row_begin) ++it;
+                        const DSeg &tseg = tsegs[it];
+                        const int64_t b = blk[it];
                         const hmat_block_desc &d = bl[b];
                         v = d.a[(m.row_begin + i - tseg.row_begin) + (int64_t)jj * d.lda];
                         inv = 1.0f / hp.sD[b];
@@ -748,9 +787,10 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
               [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
     const int32_t nc = (int32_t)hp.chunk_node.size();
     hp.anc.assign((size_t)nc * (cd + 1), 0);
-    std::vector<int32_t> cfirst(t.num_nodes, INT32_MAX), clast(t.num_nodes, -1);
+    std::vector<int32_t> cfirst(t.num_nodes, INT32_MAX), clast(t.num_nodes, -1), chunk_of(t.num_nodes, -1);
     for (int32_t c = 0; c < nc; ++c) {
         int32_t a = hp.chunk_node[c];
+        chunk_of[a] = c;
         for (int32_t d = cd; d >= 0; --d) {
             hp.anc[(size_t)c * (cd + 1) + d] = a;
             cfirst[a] = std::min(cfirst[a], c);
@@ -802,11 +842,10 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         m.row_begin = (int32_t)t.begin[node];
         m.rows = (int32_t)t.size(node);
         m.leaf_base = (int32_t)hp.leaves.size();
-        std::vector<int32_t> lv;
-        if (L == 0) lv.push_back(node);
-        else
-            for (int32_t j = 0; j < t.nkids(node); ++j) lv.push_back(t.kid(node, j));
+        const std::vector<int32_t> lv = chunk_leaves(t, node);
+        const std::vector<int32_t> &src = L == 0 ? lv : st.dense_src[node];
         m.nleaf = (int32_t)lv.size();
+        m.nsrc = (int32_t)src.size();
         int32_t kb = 0;
         for (int32_t lf : lv) {
             hmat::MRLeaf e{(int32_t)t.begin[lf], (int32_t)t.size(lf), kb, (int32_t)((t.size(lf) + KB - 1) / KB)};
@@ -818,9 +857,8 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         m.xoff = xf;
         xf += (int64_t)kb * hp.ntmax;
         m.dscale_base = (int32_t)hp.dscale.size();
-        for (int32_t it = 0; it < m.nleaf; ++it)
-            for (int32_t is = 0; is < m.nleaf; ++is)
-                hp.dscale.push_back(L == 0 ? hp.sD[0] : hp.sD[st.block_of(t, lv[it], lv[is])]);
+        for (int32_t lt : lv)
+            for (int32_t ls : src) hp.dscale.push_back(hp.sD[L == 0 ? 0 : st.find(lt, ls)]);
         hp.chunks.push_back(m);
     }
     hp.x_frags = xf;
@@ -834,12 +872,8 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             if (t.depth[i] == lvl) boxes.push_back(i);
         std::sort(boxes.begin(), boxes.end(), [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
         for (int32_t s : boxes) {
-            const int32_t p = t.parent[s];
             auto &cm = hp.colmap[s];
-            for (int32_t j = 0; j < t.nkids(p); ++j) {
-                const int32_t tt = t.kid(p, j);
-                if (tt == s) continue;
-                const int64_t b = st.block_of(t, tt, s);
+            for (const int64_t b : st.by_source[s]) {
                 vcol[b] = (int32_t)cm.size();
                 for (int32_t k = 0; k < bl[b].rank; ++k) cm.emplace_back(b, k);
             }
@@ -909,11 +943,7 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         int32_t seg_kb = 0;
         for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
             const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
-            const int32_t p = t.parent[a];
-            for (int32_t j = 0; j < t.nkids(p); ++j) {
-                const int32_t s = t.kid(p, j);
-                if (s == a) continue;
-                const int64_t b = st.block_of(t, a, s);
+            for (const int64_t b : st.by_target[a]) {
                 const hmat::MRZItem &z = hp.zitems[zitem_of[b]];
                 hmat::MRSeg sg{z.zoff, (bl[b].rank + KB - 1) / KB, 0, zitem_of[b], 0};
                 seg_kb += sg.nkb;
@@ -922,13 +952,17 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                 hp.seg_node.push_back(-1);
             }
         }
-        for (int32_t lf = 0; lf < m.nleaf; ++lf) {
-            const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
-            hmat::MRSeg sg{m.xoff + (int64_t)e.kb0 * hp.ntmax, e.nkb, 1, c, lf};
+        // x over each source leaf of the dense blocks, from the X fragments of the chunk holding it
+        const std::vector<int32_t> src = L == 0 ? chunk_leaves(t, hp.chunk_node[c]) : st.dense_src[hp.chunk_node[c]];
+        for (int32_t is = 0; is < m.nsrc; ++is) {
+            const int32_t sc = L == 0 ? c : chunk_of[t.parent[src[is]]];
+            const hmat::MRChunk &ms = hp.chunks[sc];
+            const hmat::MRLeaf &e = hp.leaves[ms.leaf_base + (L == 0 ? 0 : t.child_pos[src[is]])];
+            hmat::MRSeg sg{ms.xoff + (int64_t)e.kb0 * hp.ntmax, e.nkb, 1, sc, is};
             seg_kb += sg.nkb;
             hp.segs.push_back(sg);
             hp.seg_block.push_back(-1);
-            hp.seg_node.push_back(hp.leaf_node[m.leaf_base + lf]);
+            hp.seg_node.push_back(src[is]);
         }
         m.nseg = (int32_t)hp.segs.size() - m.seg_base;
         m.step_base = (int32_t)hp.ustep.size();
@@ -1056,7 +1090,7 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
             const hmat::MRSeg &sg = hp.segs[si];
             const int64_t lb = hp.seg_block[si];
             int64_t db = -1;
-            if (sg.kind == 1) db = (t.L == 0) ? 0 : st.block_of(t, tnode, hp.seg_node[si]);
+            if (sg.kind == 1) db = (t.L == 0) ? 0 : st.find(tnode, hp.seg_node[si]);
             const hmat_block_desc &d = bl[sg.kind == 0 ? lb : db];
             const int32_t ncols = sg.kind == 0 ? d.rank : (int32_t)t.size(hp.seg_node[si]);
             const int32_t rbase = (int32_t)(sg.kind == 0 ? t.begin[d.target] : t.begin[tnode]);

@@ -45,11 +45,11 @@ struct ChunkMeta {
     int32_t nq_lr;       // of which belong to the low-rank part
     int64_t ud_off;      // element offset of the chunk's UD panel
     int32_t zseg_base;   // index of its first z segment (L-1 of them)
-    int32_t dseg_base;   // index of its first dense segment (one per source leaf)
-    int32_t nleaf;       // number of leaves (dense segments)
-    int32_t dscale_base; // index of its nleaf x nleaf dense scales
+    int32_t dseg_base;   // index of its first dense segment: nleaf source leaves, then ntleaf target leaves
+    int32_t nleaf;       // number of source leaves of its dense blocks (dense segments)
+    int32_t dscale_base; // index of its ntleaf x nleaf dense scales
     int32_t part_base;   // offset of its partial sums
-    int32_t pad_;
+    int32_t ntleaf;      // number of target leaves (its children)
 };
 
 struct ZSeg {            // a run of the U-phase vector taken from zg
@@ -145,15 +145,17 @@ struct MRChunk {
     int32_t rows;
     int32_t nkb;          // K-blocks of its leaf-padded rows
     int32_t leaf_base;    // first entry in the leaf table
-    int32_t nleaf;
+    int32_t nleaf;        // its leaves (the target leaves of its rows)
     int32_t seg_base;     // first U-phase segment
     int32_t nseg;
-    int32_t dscale_base;  // nleaf x nleaf dense-block scales
+    int32_t dscale_base;  // nleaf x nsrc dense-block scales
     int64_t xoff;         // first B fragment of its Xpack (relative to xpack)
     int32_t step_base;    // first entry of its U-phase step table
     int32_t nsteps;       // K-block steps over all its segments
     int32_t ulo_base;     // FP8 forms: first of its 32 x nzsteps U lo-scales in ulo
     int32_t nzsteps;      // steps over z segments (they come first)
+    int32_t nsrc;         // source leaves of its dense blocks
+    int32_t pad_;
 };
 
 struct MRLeaf {
@@ -186,8 +188,8 @@ struct MRSeg {
     int64_t src;          // first B fragment (Zpack or Xpack)
     int32_t nkb;          // K-blocks
     int32_t kind;         // 0: z of a block, 1: x over a source leaf
-    int32_t sidx;         // block id (z) or chunk id (x): scale row
-    int32_t leaf;         // source leaf index in the chunk (x)
+    int32_t sidx;         // block id (z) or chunk id (x, the chunk holding the leaf): scale row
+    int32_t leaf;         // x: index of the leaf among the chunk's dense sources
 };
 
 struct MRTile {

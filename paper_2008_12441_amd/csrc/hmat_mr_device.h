@@ -601,7 +601,7 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
     // A fragments are contiguous over the tile's steps; the chunk's step
     // table gives each step's B fragment (z of a block, or x of a source leaf).
     const MRStep *steps = p.ustep + ch.step_base;
-    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nleaf;  // this target leaf's dense scales
+    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;  // this target leaf's dense scales
     float sv = 1.0f;  // lane j: n-tile scale of the chunk's segment j
     if (LANE_SCALES && F::SCALED && lane < ch.nseg) {
         const MRSeg sg = p.segs[ch.seg_base + lane];  // per lane: a vector load

@@ -278,9 +278,10 @@ __device__ inline void sv_chunk(const DevPlan &p, int c, int tid, Acc *vec, cons
             (int64_t)tile * m.nq * kWave + lane;
         const int row = tile * kWave + lane;
         Acc acc = dot_range<STORE, Acc>(base, vec, 0, m.nq_lr);
-        int tleaf = 0;
+        int tleaf = 0;  // the row's target leaf: the target segments follow the source segments
         if (STORE == HMAT_STORE_FP16_SCALED)
-            while (tleaf + 1 < m.nleaf && m.row_begin + row >= cload(p.dsegs, m.dseg_base + tleaf + 1).row_begin)
+            while (tleaf + 1 < m.ntleaf &&
+                   m.row_begin + row >= cload(p.dsegs, m.dseg_base + m.nleaf + tleaf + 1).row_begin)
                 ++tleaf;
         int q = m.nq_lr;
         for (int s = 0; s < m.nleaf; ++s) {

@@ -139,13 +139,14 @@ def test_block_errors(small):
     # dense block between non-leaf siblings is unsupported
     b8 = blocks.copy(); b8["rank"][lr] = 0
     assert _create_status(tree, b8)[0] == 4
-    # a block between non-siblings (standard admissibility) is unsupported
+    # a block moved to a cousin source: its pair is no longer a child pair of a
+    # recursion pair, and the pair it leaves is missing
     t = d.tree
     lr2 = int(np.nonzero((rank > 0) & (t.depth[d.blocks.target] == 2))[0][0])
     cousin = [i for i in range(t.num_nodes) if t.depth[i] == 2
               and t.parent[i] != t.parent[int(blocks["target"][lr2])]][0]
     b9 = blocks.copy(); b9["source"][lr2] = cousin
-    assert _create_status(tree, b9)[0] == 4
+    assert _create_status(tree, b9)[0] == 3
     # a (c, c) block above the leaves
     b10 = blocks.copy(); b10["source"][lr] = b10["target"][lr]
     assert _create_status(tree, b10)[0] == 3

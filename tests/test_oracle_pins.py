@@ -2,7 +2,7 @@
 
 P1  assembled dense H-matrix: placing every block of Def. 2.3 in an N x N array
     and multiplying with numpy gives the oracle's y (and shows the blocks tile
-    N x N exactly once);
+    N x N exactly once), under weak and standard admissibility;
 P2  full-rank special case: with U = K_ts, V = I every block is exact, so the
     H-matvec equals the plain kernel matvec fl32(K) x;
 P3  Eckart-Young: with exact truncated-SVD factors the error against K x obeys
@@ -31,13 +31,16 @@ def c1():
     return make_hmatrix(tree, 16, kind="log", method="svd")
 
 
-@pytest.mark.parametrize("d,n,r,method,kind", [
-    (2, 64, 16, "svd", "log"), (2, 32, 8, "random", "log"), (3, 16, 8, "random", "inv"),
-    (3, 16, 8, "svd", "inv"), (1, 512, 4, "random", "log"), (2, 8, 4, "random", "log"),
-    (2, 16, 4, "random", "log")])
-def test_p1_assembled_dense(d, n, r, method, kind):
+@pytest.mark.parametrize("d,n,r,method,kind,adm", [
+    (2, 64, 16, "svd", "log", "weak"), (2, 32, 8, "random", "log", "weak"),
+    (3, 16, 8, "random", "inv", "weak"), (3, 16, 8, "svd", "inv", "weak"),
+    (1, 512, 4, "random", "log", "weak"), (2, 8, 4, "random", "log", "weak"),
+    (2, 16, 4, "random", "log", "weak"), (2, 64, 8, "random", "log", "standard"),
+    (2, 64, 4, "svd", "log", "standard"), (3, 16, 4, "random", "inv", "standard"),
+    (1, 2048, 4, "random", "log", "standard")])
+def test_p1_assembled_dense(d, n, r, method, kind, adm):
     tree = uniform_tree(d, n)
-    data = make_hmatrix(tree, r, kind=kind, method=method, seed=7)
+    data = make_hmatrix(tree, r, kind=kind, method=method, seed=7, admissibility=adm)
     kh = oracle.assemble_dense(data)
     assert not np.isnan(kh).any(), "blocks do not cover N x N"
     x = make_rhs(tree.n, 3, 11)
@@ -46,10 +49,12 @@ def test_p1_assembled_dense(d, n, r, method, kind):
     assert rel(y, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("d,n,kind", [(2, 64, "log"), (3, 16, "inv"), (2, 32, "inv")])
-def test_p2_full_rank_equals_kernel_matvec(d, n, kind):
+@pytest.mark.parametrize("d,n,kind,adm", [(2, 64, "log", "weak"), (3, 16, "inv", "weak"),
+                                          (2, 32, "inv", "weak"), (2, 64, "log", "standard"),
+                                          (1, 2048, "inv", "standard")])
+def test_p2_full_rank_equals_kernel_matvec(d, n, kind, adm):
     tree = uniform_tree(d, n)
-    data = make_hmatrix(tree, 0, kind=kind, method="fullrank")
+    data = make_hmatrix(tree, 0, kind=kind, method="fullrank", admissibility=adm)
     k32 = dense_kernel(tree, kind).astype(np.float32).astype(np.float64)
     x = make_rhs(tree.n, 2, 5)
     y = oracle.oracle_matvec(data, x)

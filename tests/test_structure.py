@@ -1,4 +1,4 @@
-"""Tree and block structure of the weak-admissibility H-matrix (Def. 2.3, Sec. 2)."""
+"""Tree and block structure of the H-matrix (Def. 2.3, Sec. 2): weak and standard admissibility."""
 import os
 
 import numpy as np
@@ -121,3 +121,94 @@ def test_batch_generator_shapes():
     for s in specs[:12]:
         tree = build_tree(s["shape"], n_full=s["n_full"], offset=s["offset"])
         assert all(tree.size(p) <= 64 for p in range(tree.num_nodes) if not tree.children[p])
+
+
+# ---------------------------------------------------------------------------
+# Standard admissibility (Sec. 2, Def. "Standard admissibility condition", with
+# rho = sqrt(d) as the paper fixes it).
+# ---------------------------------------------------------------------------
+
+def _standard_bruteforce(tree, r):
+    """Def. 2.3 with the standard condition, by plain recursion over one pair at a
+    time and float geometry of the boxes (min(diam) <= sqrt(d) dist)."""
+    d = tree.d
+    nf = np.asarray(tree.n_full, float)
+
+    def box(a):
+        lo = tree.lo[a] / nf
+        return lo, lo + tree.shape[a] / nf
+
+    def admissible(t, s):
+        (lt, ht), (ls, hs) = box(t), box(s)
+        diam = min(np.linalg.norm(ht - lt), np.linalg.norm(hs - ls))
+        gap = np.maximum(np.maximum(ls - ht, lt - hs), 0.0)
+        return diam <= np.sqrt(d) * np.linalg.norm(gap) * (1 + 1e-12)
+
+    out = {}
+    todo = [(0, 0)]
+    while todo:
+        p, q = todo.pop()
+        for ct in tree.children[p]:
+            for cs in tree.children[q]:
+                if tree.is_leaf(ct) or tree.is_leaf(cs):
+                    out[(ct, cs)] = 0
+                elif admissible(ct, cs):
+                    out[(ct, cs)] = min(r, tree.size(ct), tree.size(cs))
+                else:
+                    todo.append((ct, cs))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (32, 32), (8, 8, 8), (256,), (40, 23), (9, 13, 6)])
+def test_standard_blocks_match_bruteforce(shape):
+    tree = build_tree(shape, leaf_max=4 if len(shape) > 1 else 8)
+    blocks = enumerate_blocks(tree, 3, "standard")
+    got = {(int(t), int(s)): int(k) for t, s, k in zip(blocks.target, blocks.source, blocks.rank)}
+    assert len(got) == len(blocks)
+    assert got == _standard_bruteforce(tree, 3)
+
+
+@pytest.mark.parametrize("d,n", [(2, 256), (2, 1024), (3, 32), (3, 64), (1, 4096)])
+def test_standard_block_counts_closed_form(d, n):
+    """On the ideal domain with m = 2^l boxes per axis, the ordered pairs whose
+    parents are neighbours number (6m - 8)^d per level and the neighbour pairs
+    (3m - 2)^d; the low-rank blocks are their difference, the dense blocks all
+    (6m - 8)^d leaf pairs."""
+    tree = uniform_tree(d, n)
+    L = tree.leaf_depth
+    blocks = enumerate_blocks(tree, 4, "standard")
+    lr = blocks.rank > 0
+    per_level = np.bincount(tree.depth[blocks.target[lr]], minlength=L + 1)
+    for lvl in range(1, L):
+        m = 2 ** lvl
+        assert per_level[lvl] == (6 * m - 8) ** d - (3 * m - 2) ** d
+    assert per_level[L] == 0
+    assert int(np.sum(~lr)) == (6 * 2 ** L - 8) ** d
+    # same depth on both sides; dense only between leaves
+    assert np.all(tree.depth[blocks.target] == tree.depth[blocks.source])
+    assert np.all(tree.depth[blocks.target[~lr]] == L)
+
+
+def test_standard_admissibility_boundary():
+    """Boxes of side h one box apart are admissible (h sqrt(d) <= sqrt(d) h, equality);
+    boxes that touch, even at a corner, are not."""
+    from hmat_inputs.tree import standard_admissible
+    tree = uniform_tree(2, 256)   # level 2: 4 x 4 boxes of 64 x 64 cells
+    lvl2 = [int(a) for a in tree.nodes_at_depth(2)]
+    pos = {tuple(int(v) // 64 for v in tree.lo[a]): a for a in lvl2}
+    a = pos[(0, 0)]
+    assert standard_admissible(tree, [a], [pos[(2, 0)]])[0]
+    assert standard_admissible(tree, [a], [pos[(2, 2)]])[0]
+    assert not standard_admissible(tree, [a], [pos[(1, 1)]])[0]
+    assert not standard_admissible(tree, [a], [pos[(1, 0)]])[0]
+    assert not standard_admissible(tree, [a], [a])[0]
+
+
+def test_standard_stored_elements():
+    """Storage of the 1024^2, rank-4 workload: 2 r sum_l count_l N / 4^l + 64^2 dense count."""
+    tree = uniform_tree(2, 1024)
+    blocks = enumerate_blocks(tree, 4, "standard")
+    N, L = tree.n, tree.leaf_depth
+    lr = sum(((6 * 2 ** l - 8) ** 2 - (3 * 2 ** l - 2) ** 2) * 2 * 4 * (N // 4 ** l) for l in range(1, L))
+    dense = (6 * 2 ** L - 8) ** 2 * 64 * 64
+    assert stored_elements(tree, blocks) == lr + dense
