@@ -360,10 +360,10 @@ def run_multi_rhs(stream, steps, warmup, with_oracle=True, method=None):
 
 
 # The paper's fastest time for the same grid, rank and admissibility condition
-# (Tables 2 and 3, standard-admissibility columns; distributed memory on CPU
+# (Tables 1 and 2, standard-admissibility columns; distributed memory on CPU
 # processes): context for the single-GPU number, not its target.
-PAPER_STANDARD = {"s2": {"time_s": 6.16e-3, "processes": 512, "table": "Table 2 (2D), N = 1024^2, r = 4"},
-                  "s3": {"time_s": 7.06e-3, "processes": 128, "table": "Table 3 (3D), N = 64^3, r = 4"}}
+PAPER_STANDARD = {"s2": {"time_s": 6.16e-3, "processes": 512, "table": "Table 1 (2D), N = 1024^2, r = 4"},
+                  "s3": {"time_s": 7.06e-3, "processes": 128, "table": "Table 2 (3D), N = 64^3, r = 4"}}
 
 
 def run_standard(stream, name, steps, warmup, with_oracle=True):
