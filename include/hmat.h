@@ -1,12 +1,13 @@
 /*
  * hmat.h -- C ABI of the MI355X (gfx950) H-matrix-vector product library.
  *
- * The library applies an H-matrix under the weak admissibility condition
- * (Li, Poulson, Ying, "Distributed-memory H-matrix algebra I", Sec. 2):
- * the matrix is defined by a domain tree (Def. "Domain tree") and by the
- * blocks that Def. 2.3 produces -- dense blocks D between leaves of one
- * parent, and low-rank blocks U V^T between distinct siblings at every
- * non-leaf level. The product is Eq. (2.4), y_t += D_ts x_s and
+ * The library applies an H-matrix (Li, Poulson, Ying, "Distributed-memory
+ * H-matrix algebra I", Sec. 2): the matrix is defined by a domain tree
+ * (Def. "Domain tree") and by the blocks that Def. 2.3 produces -- dense
+ * blocks D between leaves, and low-rank blocks U V^T between admissible
+ * non-leaf boxes -- under the weak or the standard admissibility condition
+ * (or any other that gives a block set of Def. 2.3's shape). The product is
+ * Eq. (2.4), y_t += D_ts x_s and
  * y_t += U_ts (V_ts^T x_s) over all blocks, in the GEMV form
  * y = alpha K x + beta y of the remark that closes Sec. 4.1.
  *
@@ -129,20 +130,24 @@ typedef struct hmat_handle *hmat_t;
 
 /* Build a device-resident H-matrix from a domain tree and its blocks.
  *
- * The block set must be exactly the weak-admissibility structure of Def. 2.3
- * for the tree: for every node p above the leaves, a low-rank block (t, s)
- * for each ordered pair of distinct children t != s of p when those children
- * are not leaves, and a dense block for each ordered pair (t, s) of children
- * (t == s included) when they are leaves; a root that is itself a leaf takes
- * one dense block (0, 0). Blocks may come in any order.
+ * The block set must have the shape of Def. 2.3 for the tree: starting from
+ * the recursion pair (root, root), every ordered pair (t, s) of a child t of
+ * p and a child s of q, for a recursion pair (p, q), is either a block or
+ * itself a recursion pair; pairs of leaves are dense blocks, blocks between
+ * non-leaf boxes are low-rank (t != s); every block is such a child pair.
+ * Under weak admissibility the recursion pairs are the (c, c) pairs; under
+ * standard admissibility (Eq. (2.2)) they are the pairs of neighbouring
+ * boxes. A root that is itself a leaf takes one dense block (0, 0). Blocks
+ * may come in any order. The library does not evaluate an admissibility
+ * condition itself.
  *
  * Errors: INVALID_ARG (null pointers, sizes, leading dimensions, ranks,
  * options); BAD_TREE; BAD_BLOCKS (a block on a recursion pair (c, c) above
- * the leaves, a duplicate, or a missing pair); UNSUPPORTED (leaves at mixed
- * depths, blocks between non-siblings as under standard admissibility, a
- * dense block between non-leaves, a low-rank block between leaves, a chunk
- * whose vector operand exceeds the kernel's LDS budget -- 16384 FP32 values,
- * or 8192 FP64 values under HMAT_FLAG_FP64_ACCUM); NOMEM; DEVICE.
+ * the leaves, a duplicate, a missing pair, or a block that is no child pair
+ * of a recursion pair); UNSUPPORTED (leaves at mixed depths, a dense block
+ * between non-leaves, a low-rank block between leaves, a chunk whose vector
+ * operand exceeds the kernel's LDS budget -- 16384 FP32 values, or 8192 FP64
+ * values under HMAT_FLAG_FP64_ACCUM); NOMEM; DEVICE.
  *
  * Ownership: all inputs are deep-copied and re-laid-out; the handle owns its
  * device memory until hmat_destroy. On failure *out is set to NULL and
@@ -200,9 +205,9 @@ hmat_status hmat_probe_bandwidth(const void *src, void *dst, int64_t bytes, int3
  * products, of the partial reduction and of the target-side products, Sec.
  * 4.1, Steps 1-5) held in one queue in stage order; the kernel's workgroups
  * take items from the queue, and an item waits on its own member's earlier
- * stage through a completion counter. Under weak admissibility every box of a
- * level carries the same number of blocks (Sec. 3.2), so an item's work is
- * its byte count, which the queue is sorted by.
+ * stage through a completion counter. An item's work is estimated by its
+ * byte count (under weak admissibility every box of a level carries the same
+ * number of blocks, Sec. 3.2), which the queue is sorted by.
  * ------------------------------------------------------------------------ */
 typedef struct hmat_batch_handle *hmat_batch_t;
 

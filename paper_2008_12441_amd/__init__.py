@@ -1,4 +1,4 @@
-"""MI355X (gfx950) H-matrix-vector product under weak admissibility.
+"""MI355X (gfx950) H-matrix-vector product (weak and standard admissibility).
 
 The product y = alpha K x + beta y of an H-matrix (Def. 2.3, Eq. (2.4)) runs
 in hand-written HIP kernels behind the C ABI of ``include/hmat.h``; this

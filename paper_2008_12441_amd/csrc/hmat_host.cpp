@@ -279,7 +279,7 @@ hmat_status analyse_tree(const hmat_tree_desc *td, Tree &t) {
         if (!t.leaf(i)) continue;
         if (L < 0) L = t.depth[i];
         else if (t.depth[i] != L)
-            return fail(HMAT_ERR_UNSUPPORTED, "leaves at different depths are not supported (the weak-admissibility "
+            return fail(HMAT_ERR_UNSUPPORTED, "leaves at different depths are not supported (the Def. 2.3 "
                                               "structure then has dense blocks between a leaf and a non-leaf)");
     }
     t.L = L;
