@@ -103,11 +103,21 @@ typedef struct hmat_block_desc {
  * any max_nrhs) and is meant for checking, not for speed. */
 #define HMAT_FLAG_FP64_ACCUM 1
 
+/* HMAT_FLAG_TRANSPOSE -- the handle applies the transpose: y = alpha K^T x +
+ * beta y. K^T is the H-matrix whose blocks are the given blocks transposed:
+ * block (t, s) becomes (s, t), a low-rank block's U and V trade places and a
+ * dense block is transposed (Eq. (2.4) with the roles of target and source
+ * exchanged; the transposed block set has Def. 2.3's shape whenever the given
+ * one does). Validation and error messages refer to the blocks as given; the
+ * storage forms quantise the transposed factors (the same scales, since each
+ * is per block or per factor column). Combines with every other option. */
+#define HMAT_FLAG_TRANSPOSE 2
+
 typedef struct hmat_options {
     int32_t storage;        /* hmat_storage */
     int32_t max_nrhs;       /* largest nrhs hmat_matvec will be called with, >= 1 */
     int32_t device;         /* HIP device ordinal the data lives on */
-    int32_t flags;          /* 0 or HMAT_FLAG_FP64_ACCUM; other bits give INVALID_ARG */
+    int32_t flags;          /* HMAT_FLAG_FP64_ACCUM | HMAT_FLAG_TRANSPOSE; other bits give INVALID_ARG */
 } hmat_options;
 
 typedef struct hmat_info {
@@ -240,7 +250,7 @@ typedef struct hmat_batch_info {
  * max_nrhs == 1 (single-vector kernels); 1 <= nrhs[i] <= min(16, max_nrhs) for
  * one created with max_nrhs > 1 (MFMA kernels, one tile of 16 columns).
  * Members must be distinct, live on one device, share one storage form and
- * have no flags. A batch uses its members' device workspaces: while it exists
+ * not use HMAT_FLAG_FP64_ACCUM (HMAT_FLAG_TRANSPOSE members are fine). A batch uses its members' device workspaces: while it exists
  * the members cannot be destroyed (hmat_destroy gives INVALID_ARG), and a
  * member must not run hmat_matvec concurrently with the batch. opts may be
  * NULL (defaults: graph on, as many workgroups as fit, largest item first).

@@ -116,6 +116,28 @@ def oracle_matvec(data, x, *, alpha: float = 1.0, beta: float = 0.0, y_in=None,
     return y
 
 
+def transposed(data):
+    """The factor set of K^T: block (t, s) becomes (s, t), a low-rank block's U and
+    V trade places, and a dense block's entries are stored transposed (same pool
+    offsets, so every block keeps its slot)."""
+    import copy
+
+    out = copy.copy(data)
+    blocks = copy.copy(data.blocks)
+    blocks.target, blocks.source = data.blocks.source.copy(), data.blocks.target.copy()
+    out.blocks = blocks
+    lr = data.blocks.rank > 0
+    out.off_a = np.where(lr, data.off_b, data.off_a)
+    out.off_b = np.where(lr, data.off_a, -1)
+    pool = data.pool.copy()
+    for b in np.nonzero(~lr)[0]:
+        o = int(data.off_a[b])
+        d = data.dense(int(b))                      # |t| x |s|
+        pool[o:o + d.size] = np.ascontiguousarray(d).reshape(-1)   # D^T column-major = D row-major
+    out.pool = pool
+    return out
+
+
 def assemble_dense(data) -> np.ndarray:
     """Place every block of the H-matrix into an N x N FP64 matrix (small N only).
 

@@ -31,6 +31,7 @@ STORAGE = {"fp32": HMAT_STORE_FP32, "fp16": HMAT_STORE_FP16_SCALED, "bf16": HMAT
            "fp8": HMAT_STORE_FP8, "fp8_f16d": HMAT_STORE_FP8_F16D}
 
 HMAT_FLAG_FP64_ACCUM = 1
+HMAT_FLAG_TRANSPOSE = 2
 
 HMAT_NUM_PHASES = 3
 
@@ -243,9 +244,10 @@ def hmat_probe_bandwidth(src_ptr: int, dst_ptr: int, nbytes: int, mode: int, str
 class HMatrix:
     """Owner of one handle; matvec takes torch CUDA tensors (n x k, column-major or a vector)."""
 
-    def __init__(self, tree_desc, blocks, *, storage="fp32", max_nrhs=1, device=0, fp64_accum=False):
+    def __init__(self, tree_desc, blocks, *, storage="fp32", max_nrhs=1, device=0, fp64_accum=False,
+                 transpose=False):
         st = STORAGE[storage] if isinstance(storage, str) else int(storage)
-        flags = HMAT_FLAG_FP64_ACCUM if fp64_accum else 0
+        flags = (HMAT_FLAG_FP64_ACCUM if fp64_accum else 0) | (HMAT_FLAG_TRANSPOSE if transpose else 0)
         self.handle = hmat_create(tree_desc, blocks, storage=st, max_nrhs=max_nrhs, device=device, flags=flags)
         self.info = hmat_get_info(self.handle)
         self.n = int(self.info["n"])

@@ -279,7 +279,8 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
         } else if (h->device != b->device || h->storage != b->storage) {
             return set_error(HMAT_ERR_INVALID_ARG, "members must share one device and one storage form");
         }
-        if (h->flags != 0) return set_error(HMAT_ERR_INVALID_ARG, "members must be created without flags");
+        if (h->flags & HMAT_FLAG_FP64_ACCUM)
+            return set_error(HMAT_ERR_INVALID_ARG, "members must not use the FP64 accuracy-check mode");
         if (h->storage > HMAT_STORE_BF16)
             return set_error(HMAT_ERR_UNSUPPORTED, "batches take FP32, FP16 and BF16 members");
         if (!h->mr) {

@@ -1265,6 +1265,40 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     return HMAT_OK;
 }
 
+// The blocks of K^T: (t, s) becomes (s, t); a low-rank block's U and V trade
+// places; a dense block is copied transposed into `dense` (column-major, leading
+// dimension |s|).
+void transpose_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb, std::vector<hmat_block_desc> &out,
+                      std::vector<float> &dense) {
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int64_t b = 0; b < nb; ++b)
+        off[b + 1] = off[b] + (bl[b].rank == 0 ? t.size(bl[b].target) * t.size(bl[b].source) : 0);
+    dense.resize(off[nb]);
+    out.resize(nb);
+    parallel_for(nb, [&](int64_t b) {
+        const hmat_block_desc &d = bl[b];
+        hmat_block_desc &o = out[b];
+        o = d;
+        o.target = d.source;
+        o.source = d.target;
+        if (d.rank > 0) {
+            o.a = d.b;
+            o.lda = d.ldb;
+            o.b = d.a;
+            o.ldb = d.lda;
+        } else {
+            const int64_t m = t.size(d.target), n = t.size(d.source);
+            float *dst = dense.data() + off[b];
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < n; ++i) dst[i + j * n] = d.a[j + i * d.lda];
+            o.a = dst;
+            o.lda = n;
+            o.b = nullptr;
+            o.ldb = 0;
+        }
+    });
+}
+
 hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *blocks, int64_t nb,
                         const hmat_options *opts, hmat_handle *h) {
     if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
@@ -1272,7 +1306,8 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
         return fail(HMAT_ERR_INVALID_ARG, "unknown storage form");
     if (opts->max_nrhs < 1) return fail(HMAT_ERR_INVALID_ARG, "max_nrhs must be >= 1");
     if (opts->device < 0) return fail(HMAT_ERR_INVALID_ARG, "device must be >= 0");
-    if ((opts->flags & ~HMAT_FLAG_FP64_ACCUM) != 0) return fail(HMAT_ERR_INVALID_ARG, "unknown option flags");
+    if ((opts->flags & ~(HMAT_FLAG_FP64_ACCUM | HMAT_FLAG_TRANSPOSE)) != 0)
+        return fail(HMAT_ERR_INVALID_ARG, "unknown option flags");
     const bool fp64 = (opts->flags & HMAT_FLAG_FP64_ACCUM) != 0;
     const int32_t acc_bytes = fp64 ? 8 : 4;
     Tree t;
@@ -1281,11 +1316,21 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     Structure st;
     s = validate_blocks(t, blocks, nb, st);
     if (s != HMAT_OK) return s;
+    std::vector<hmat_block_desc> tblocks;  // K^T: the transposed blocks, and the transposed dense entries
+    std::vector<float> tdense;
+    if (opts->flags & HMAT_FLAG_TRANSPOSE) {
+        transpose_blocks(t, blocks, nb, tblocks, tdense);
+        blocks = tblocks.data();
+        st = Structure();
+        s = validate_blocks(t, blocks, nb, st);
+        if (s != HMAT_OK) return s;
+    }
     HostPlan hp;
     HostPlanMR hpm;
     const bool fp8 = opts->storage == HMAT_STORE_FP8 || opts->storage == HMAT_STORE_FP8_F16D;
     if (fp8 && (opts->max_nrhs < 2 || fp64))
-        return fail(HMAT_ERR_UNSUPPORTED, "the FP8 storage forms need a multi-RHS handle (max_nrhs > 1, no flags)");
+        return fail(HMAT_ERR_UNSUPPORTED,
+                    "the FP8 storage forms need a multi-RHS handle (max_nrhs > 1, no FP64 accumulation)");
     h->mr = opts->max_nrhs > 1 && !fp64;
     s = h->mr ? build_plan_mr(t, st, blocks, nb, opts->storage, opts->max_nrhs, hpm)
               : build_plan(t, st, blocks, nb, opts->storage, acc_bytes, hp);

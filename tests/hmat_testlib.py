@@ -12,9 +12,9 @@ def descriptors(data):
                                data.blocks.rank, data.pool, data.off_a, data.off_b)
 
 
-def create(data, storage="fp32", max_nrhs=1, fp64_accum=False):
+def create(data, storage="fp32", max_nrhs=1, fp64_accum=False, transpose=False):
     tree, blocks, keep = descriptors(data)
-    return hm.HMatrix(tree, blocks, storage=storage, max_nrhs=max_nrhs, fp64_accum=fp64_accum)
+    return hm.HMatrix(tree, blocks, storage=storage, max_nrhs=max_nrhs, fp64_accum=fp64_accum, transpose=transpose)
 
 
 def gpu_matvec(h, x, *, alpha=1.0, beta=0.0, y0=None, ld_pad=0):

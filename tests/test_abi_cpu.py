@@ -69,9 +69,15 @@ def test_null_and_option_errors(small):
     assert lib.hmat_create(ctypes.byref(tree), blocks.ctypes.data, len(blocks), ctypes.byref(opts), None) == 1
     _expect(_create_status(tree, blocks, storage=7), 1, "storage")
     _expect(_create_status(tree, blocks, max_nrhs=0), 1, "max_nrhs")
-    _expect(_create_status(tree, blocks, flags=3), 1, "flags")
-    _expect(_create_status(tree, blocks, flags=2), 1, "flags")
+    _expect(_create_status(tree, blocks, flags=4), 1, "flags")
+    _expect(_create_status(tree, blocks, flags=7), 1, "flags")
     _expect(_create_status(tree, blocks, flags=-1), 1, "flags")
+    # the transpose flag, alone and with the FP64 mode, passes validation (0 with a GPU, 6 without)
+    for fl in (2, 3):
+        st, msg = _create_status(tree, blocks, flags=fl)
+        assert st in (0, 6), msg
+    st, msg = _create_status(tree, blocks, storage=3, max_nrhs=8, flags=2)
+    assert st in (0, 6), msg
     _expect(_create_status(tree, blocks, device=-1), 1, "device")
 
 

@@ -1,0 +1,135 @@
+"""GPU parity of the transpose product (HMAT_FLAG_TRANSPOSE): y = alpha K^T x + beta y.
+
+A transposed handle is checked against the FP64 oracle over the factor set of
+K^T (blocks (s, t), U and V exchanged, dense blocks transposed), with the same
+bar as the other parity tests, for both admissibility conditions, every storage
+form, single and multi-RHS, the FP64 mode and the batched launch; and the two
+handles of one matrix satisfy <a, K b> = <K^T a, b> to FP32 accuracy.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2008_12441_amd as hm
+from oracle.quant import dequantised
+from hmat_inputs import build_tree, make_hmatrix, make_rhs, uniform_tree
+from hmat_testlib import assert_close, assert_fp32_rounding_of, create, gpu_matvec
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+ELEM_TOL = 1e-4
+KERNEL_TOL = {"fp32": 1e-5, "fp16": 1e-5, "bf16": 3e-5, "fp8": 1e-5, "fp8_f16d": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    yield
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _data(shape, r, adm, seed):
+    if len(set(shape)) == 1 and shape[0] & (shape[0] - 1) == 0:
+        tree = uniform_tree(len(shape), shape[0])
+    else:
+        full = tuple(max(256 if len(shape) == 2 else 64, s) for s in shape)
+        tree = build_tree(shape, n_full=full)
+    kind = "inv" if len(shape) == 3 else "log"
+    return make_hmatrix(tree, r, kind=kind, method="random", seed=seed, admissibility=adm)
+
+
+CASES = [((128, 128), 8, "weak"), ((17, 33, 9), 8, "weak"), ((64, 64), 8, "standard"),
+         ((40, 23), 8, "standard"), ((16, 16, 16), 4, "standard"), ((255, 130), 16, "weak")]
+IDS = [f"{'x'.join(map(str, s))}-{a}" for s, _, a in CASES]
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape,r,adm", CASES, ids=IDS)
+def test_transpose_single_rhs(shape, r, adm, form):
+    _log(f"case transpose single-rhs {shape} {adm} {form}")
+    data = _data(shape, r, adm, 81)
+    x = make_rhs(data.n, 1, 82)
+    ref = oracle.oracle_matvec(dequantised(oracle.transposed(data), form), x)
+    with create(data, storage=form, transpose=True) as h:
+        y = gpu_matvec(h, x, ld_pad=2)
+    assert_close(y, ref, FP32_TOL, ELEM_TOL)
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16", "bf16", "fp8", "fp8_f16d"])
+@pytest.mark.parametrize("shape,r,adm,k", [((64, 64), 8, "weak", 5), ((16, 16, 16), 8, "weak", 17),
+                                           ((64, 64), 8, "standard", 16), ((40, 23), 8, "standard", 3)],
+                         ids=["64x64-weak-k5", "16^3-weak-k17", "64x64-standard-k16", "40x23-standard-k3"])
+def test_transpose_multi_rhs(shape, r, adm, k, form):
+    _log(f"case transpose multi-rhs {shape} {adm} k={k} {form}")
+    data = _data(shape, r, adm, 83)
+    x = make_rhs(data.n, k, 84)
+    ref = oracle.oracle_matvec(dequantised(oracle.transposed(data), form), x)
+    with create(data, storage=form, max_nrhs=k, transpose=True) as h:
+        y = gpu_matvec(h, x)
+    assert_close(y, ref, KERNEL_TOL[form], 10 * KERNEL_TOL[form])
+
+
+def test_transpose_fp64_accum():
+    _log("case transpose fp64 accumulation")
+    data = _data((128, 128), 8, "standard", 85)
+    x = make_rhs(data.n, 1, 86)
+    ref = oracle.oracle_matvec(oracle.transposed(data), x)
+    with create(data, fp64_accum=True, transpose=True) as h:
+        y = gpu_matvec(h, x)
+    assert_fp32_rounding_of(y, ref)
+
+
+@pytest.mark.parametrize("adm", ["weak", "standard"])
+def test_adjoint_identity(adm):
+    """<a, K b> = <K^T a, b> between the two handles of one matrix."""
+    _log(f"case adjoint identity {adm}")
+    data = _data((128, 128), 8, adm, 87)
+    a = make_rhs(data.n, 3, 88)
+    b = make_rhs(data.n, 3, 89)
+    with create(data) as h, create(data, transpose=True) as ht:
+        kb = gpu_matvec(h, b[:, :1])
+        kta = gpu_matvec(ht, a[:, :1])
+    lhs = float(np.sum(a[:, 0].astype(np.float64) * kb[:, 0]))
+    rhs = float(np.sum(kta[:, 0] * b[:, 0].astype(np.float64)))
+    scale = float(np.linalg.norm(a[:, 0]) * np.linalg.norm(kb[:, 0]))
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_transpose_batch_member():
+    import torch
+
+    _log("case transpose batch")
+    datas = [_data((64, 64), 8, "weak", 90), _data((64, 64), 8, "standard", 91), _data((17, 33, 9), 8, "weak", 92)]
+    flags = [True, True, False]
+    handles = [create(d, storage="fp16", transpose=t) for d, t in zip(datas, flags)]
+    xs, ys, refs, xn = [], [], [], []
+    for j, (d, h) in enumerate(zip(datas, handles)):
+        x = make_rhs(d.n, 1, 93 + j)
+        xn.append(x)
+        xs.append(torch.from_numpy(np.ascontiguousarray(x[:, 0])).cuda())
+        ys.append(torch.full((d.n,), float("nan"), device="cuda"))
+        r = torch.full((d.n,), float("nan"), device="cuda")
+        h.matvec(xs[-1], r)
+        refs.append(r)
+    torch.cuda.synchronize()
+    with hm.HBatch(handles, [1, 1, 1]) as b:
+        b.matvec(xs, ys)
+        b.sync()
+        torch.cuda.synchronize()
+    for y, r in zip(ys, refs):
+        assert torch.equal(y, r)
+    for d, t, x, y in zip(datas, flags, xn, ys):
+        src = oracle.transposed(d) if t else d
+        ref = oracle.oracle_matvec(dequantised(src, "fp16"), x)
+        assert_close(y.cpu().numpy().astype(np.float64)[:, None], ref, FP32_TOL, 10 * FP32_TOL)
+    for h in handles:
+        h.close()

@@ -11,7 +11,10 @@ P3  Eckart-Young: with exact truncated-SVD factors the error against K x obeys
 P5  algebra of the GEMV form (remark closing Sec. 4.1): linearity, columns of a
     multi-RHS product, alpha/beta;
 P8  symmetry: both kernels are symmetric and transposed blocks share their
-    factors with U and V swapped, so <a, K_H b> = <K_H a, b>.
+    factors with U and V swapped, so <a, K_H b> = <K_H a, b>;
+P9  transpose: the factor set of K^T (blocks (s, t), U and V swapped, dense
+    blocks transposed) assembles to the transpose of K, and <a, K b> = <K^T a, b>
+    holds for random (non-symmetric) factors.
 """
 import numpy as np
 import pytest
@@ -151,3 +154,18 @@ def test_threads_do_not_change_result(c1):
     y1 = oracle.oracle_matvec(c1, x, nthreads=1)
     y4 = oracle.oracle_matvec(c1, x, nthreads=4)
     assert rel(y4, y1) <= 1e-15
+
+
+@pytest.mark.parametrize("d,n,r,adm", [(2, 64, 8, "weak"), (3, 16, 4, "weak"), (2, 64, 4, "standard"),
+                                       (1, 1024, 4, "standard")])
+def test_p9_transpose(d, n, r, adm):
+    """The factor set of K^T assembles to the transpose of K's assembled matrix,
+    entry for entry, and the oracle satisfies <a, K b> = <K^T a, b>."""
+    data = make_hmatrix(uniform_tree(d, n), r, kind="log", method="random", seed=13, admissibility=adm)
+    dt = oracle.transposed(data)
+    assert np.array_equal(oracle.assemble_dense(dt), oracle.assemble_dense(data).T)
+    a = make_rhs(data.n, 2, 21).astype(np.float64)
+    b = make_rhs(data.n, 2, 22).astype(np.float64)
+    lhs = np.sum(a * oracle.oracle_matvec(data, b), axis=0)
+    rhs = np.sum(oracle.oracle_matvec(dt, a) * b, axis=0)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=0)
