@@ -133,3 +133,13 @@ def test_transpose_batch_member():
         assert_close(y.cpu().numpy().astype(np.float64)[:, None], ref, FP32_TOL, 10 * FP32_TOL)
     for h in handles:
         h.close()
+
+
+def test_c2_full_size_transpose():
+    _log("case c2-size transpose (2D 1024^2, rank 32, random fill)")
+    data = make_hmatrix(uniform_tree(2, 1024), 32, method="random", seed=27)
+    x = make_rhs(data.n, 1, 1002)
+    ref = oracle.oracle_matvec(oracle.transposed(data), x)
+    with create(data, transpose=True) as h:
+        y = gpu_matvec(h, x)
+    assert_close(y, ref, FP32_TOL, ELEM_TOL)
