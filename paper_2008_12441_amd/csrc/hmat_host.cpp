@@ -759,6 +759,7 @@ struct HostPlanMR {
     std::vector<int64_t> seg_block;            // low-rank block of a z segment, or -1
     std::vector<int32_t> seg_node;             // source leaf node of an x segment
     std::vector<hmat::MRTile> tiles;
+    std::vector<hmat::MRTileGroup> tgroups;
     std::vector<hmat::MRStep> ustep;
     std::vector<float> dscale;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> colmap;  // per node s: V column -> (block, j)
@@ -910,6 +911,28 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
     }
     hp.v_frags = af;
     hp.part_floats = (int64_t)hp.vunits.size() * 64 * hp.ntmax * 16;
+    // Launch order: the units of every level and column group that read the same
+    // kUnitChunks chunks of X run next to each other (and, with the XCD-aware
+    // numbering of the kernel, in one L2), so X is fetched from HBM about once
+    // instead of once per level. A unit keeps its partial-sum slot (poff), which
+    // the z items address by the unit's place in the level-ordered list.
+    {
+        std::vector<int32_t> perm(hp.vunits.size());
+        for (size_t i = 0; i < perm.size(); ++i) perm[i] = (int32_t)i;
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+            return hp.vunits[a].c0 / kUnitChunks < hp.vunits[b].c0 / kUnitChunks;
+        });
+        std::vector<hmat::MRVUnit> vu(perm.size());
+        std::vector<int32_t> un(perm.size()), ug(perm.size());
+        for (size_t i = 0; i < perm.size(); ++i) {
+            vu[i] = hp.vunits[perm[i]];
+            un[i] = hp.unit_node[perm[i]];
+            ug[i] = hp.unit_group[perm[i]];
+        }
+        hp.vunits.swap(vu);
+        hp.unit_node.swap(un);
+        hp.unit_group.swap(ug);
+    }
     // z items: one per low-rank block
     std::vector<int32_t> zitem_of(nb, -1);
     int64_t zf = 0;
@@ -1010,6 +1033,13 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         }
     }
     hp.ud_frags = uf;
+    // tile groups: up to four consecutive tiles of one chunk (they share the chunk's B sequence)
+    for (int32_t i = 0; i < (int32_t)hp.tiles.size();) {
+        int32_t j = i + 1;
+        while (j < (int32_t)hp.tiles.size() && j - i < 4 && hp.tiles[j].chunk == hp.tiles[i].chunk) ++j;
+        hp.tgroups.push_back(hmat::MRTileGroup{hp.tiles[i].chunk, i, j - i, 0});
+        i = j;
+    }
     return HMAT_OK;
 }
 
@@ -1223,6 +1253,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     if ((s = upload(h, hp.zitems, &p.zitems)) != HMAT_OK) return s;
     if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.tgroups, &p.tgroups)) != HMAT_OK) return s;
     if ((s = upload(h, hp.ustep, &p.ustep)) != HMAT_OK) return s;
     if (hp.fp8) {
         if ((s = upload(h, hp.vlo, &p.vlo)) != HMAT_OK) return s;
@@ -1254,8 +1285,15 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.num_vunits = (int32_t)hp.vunits.size();
     p.num_zitems = (int32_t)hp.zitems.size();
     p.num_tiles = (int32_t)hp.tiles.size();
+    p.num_tgroups = (int32_t)hp.tgroups.size();
     p.max_nzsteps = 0;
-    for (const hmat::MRChunk &c : hp.chunks) p.max_nzsteps = std::max(p.max_nzsteps, c.nzsteps);
+    p.max_nseg = 0;
+    p.max_nsteps = 0;
+    for (const hmat::MRChunk &c : hp.chunks) {
+        p.max_nzsteps = std::max(p.max_nzsteps, c.nzsteps);
+        p.max_nseg = std::max(p.max_nseg, c.nseg);
+        p.max_nsteps = std::max(p.max_nsteps, c.nsteps);
+    }
     if (hp.fp8 && (int64_t)p.max_nzsteps * 32 * 2 * 4 > 65536)
         return fail(HMAT_ERR_UNSUPPORTED, "FP8 form: a chunk's U lo-scale table exceeds the LDS budget");
     h->info.device_factor_bytes = (hp.v_frags + hp.ud_frags) * (int64_t)frag;

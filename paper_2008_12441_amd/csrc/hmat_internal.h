@@ -202,6 +202,13 @@ struct MRTile {
     int32_t pad_;
 };
 
+struct MRTileGroup {      // up to four consecutive row tiles of one chunk, run by one workgroup
+    int32_t chunk;
+    int32_t tile0;
+    int32_t ntiles;
+    int32_t pad_;
+};
+
 struct MRStep {           // one K-block step of a chunk's target-side contraction
     int64_t bofs;         // byte offset of its B fragments from zpack (xpack follows zpack)
     int32_t srow;         // row of its n-tile scales in the scale array (z rows, then x rows)
@@ -218,7 +225,9 @@ struct DevPlanMR {
     int32_t num_zitems;
     int32_t num_tiles;
     int32_t max_nzsteps;      // most z steps of a chunk (FP8 forms: U lo-scale table size / 32)
-    int32_t pad_;
+    int32_t max_nseg;         // most target-side segments of a chunk
+    int32_t num_tgroups;
+    int32_t max_nsteps;       // most target-side steps of a chunk
     const void *V;            // A fragments
     const void *UD;
     void *xpack;              // B fragments of X (in the same allocation as zpack, after it)
@@ -233,6 +242,7 @@ struct DevPlanMR {
     const MRZItem *zitems;
     const MRSeg *segs;
     const MRTile *tiles;
+    const MRTileGroup *tgroups;
     const MRStep *ustep;      // per chunk step (MRChunk::step_base)
     const float *scales;      // n-tile scales: sz rows (one per z item), then sx rows (one per chunk)
     // FP8 forms

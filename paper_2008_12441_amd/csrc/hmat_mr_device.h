@@ -277,27 +277,47 @@ __device__ inline float wave_max(float v) {
 // prep(a, m, info(s)) turns a loaded A fragment into the MFMA operand (the
 // FP8 forms dequantise there; the other forms pass it through).
 //
-// Scales are read through the scalar cache from info(s).srow, which requires
-// them to stay unchanged during the launch. With LANE_SCALES (one n-tile) the
-// caller instead loads the scales the wave needs into sv, one per lane, after
-// they were written, and step s takes lane info(s).sidx of it.
+// Without LANE_SCALES the scales are read through the scalar cache from
+// info(s).srow, which requires them to stay unchanged during the launch. With
+// LANE_SCALES the caller has loaded the scales the wave needs into sv[t] (lane
+// j: segment j's scale of n-tile t, with vector loads, so they may have been
+// written earlier in the same launch), and step s takes lane info(s).sidx of
+// them: no scalar memory access on the path of a step.
 // ---------------------------------------------------------------------------
 struct StepInfo {
     int64_t bofs;        // byte offset of the step's B fragments
     const float *srow;   // n-tile scales of the step's B (scaled form), read through the scalar cache
     float fac;           // extra power-of-two factor of those scales
-    int32_t sidx;        // LANE_SCALES: lane of sv holding the step's scale (srow unused)
+    int32_t sidx;        // LANE_SCALES: lane of sv holding the step's scales (srow unused)
     int32_t dense;       // FP8 forms: the step multiplies D (else U or V)
     int32_t lofs;        // FP8 forms, U steps: offset of the step's 32 lo-scales in the wave's LDS table
 };
 
+// B fragment t of a scaled form times a power of two f <= 1: exact while the
+// products stay normal FP16; below that, the rounding is at most 2^-24 of the
+// common scale, far under FP32 resolution of the result.
+template <class B>
+__device__ inline void scale_b(B &b, float f) {
+    const _Float16 h = (_Float16)f;
+    b.hi *= h;
+    b.lo *= h;
+}
+
+// The largest of the lanes' scales (lanes >= n hold none): the common scale of a tile.
+__device__ inline float lanes_max(float v, int lane, int n) {
+    float m = lane < n ? v : 0.0f;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) m = fmaxf(m, __shfl_xor(m, s));
+    return m > 0.0f ? m : 1.0f;
+}
+
 template <int STORE, int NT, bool LANE_SCALES, class Info, class Prep>
 __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int nm, int nsteps, int lane, Info info,
-                                  Prep prep, f32x4 (&acc)[4][NT], float (&scur)[NT], float sv) {
+                                  Prep prep, f32x4 (&acc)[4][NT], float (&scur)[NT], const float (&sv)[NT],
+                                  int nsv = 0) {
     using F = MR<STORE>;
-    static_assert(!LANE_SCALES || NT == 1, "lane scales hold one n-tile");
     auto scale_of = [&](const StepInfo &i, int t) {
-        return LANE_SCALES ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv), i.sidx))
+        return LANE_SCALES ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv[t]), i.sidx))
                            : sload(i.srow, t);
     };
     if (nsteps <= 0) return;
@@ -319,8 +339,18 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
 #pragma unroll
         for (int t = 0; t < NT; ++t) b[t] = F::loadB(rb, t * 16 * F::BFRAG, lane);
     };
+    // With lane scales (sv[t] holds nsv scales, the step's dense factor
+    // already folded in) every n-tile keeps one common scale, the largest of
+    // the tile's: each step's B is multiplied by its own scale over the common
+    // one (a power of two <= 1), and the accumulators are never rescaled.
+    // Without them, the accumulators move to each new scale as it comes.
+    constexpr bool kCommon = LANE_SCALES && F::SCALED;
+    if constexpr (kCommon) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, nsv);
+    }
     // scales of the current step's B and whether they differ from the last
-    // step's; the next step's are read one step ahead (scalar loads)
+    // step's; the next step's are read one step ahead
     StepInfo ic = info(0), in_;
     float sc[NT], sn[NT];
     bool chg_c = true, chg_n = false;
@@ -331,7 +361,14 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
     auto step = [&](typename F::A(&a)[4], typename F::B(&b)[NT], typename F::B(&bn)[NT], int st) {
         in_ = info(st + 1 < nsteps ? st + 1 : nsteps - 1);
         load_b(bn, in_.bofs);
-        if (F::SCALED) {
+        if constexpr (kCommon) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                sn[t] = scale_of(in_, t) * in_.fac;
+                const float f = sc[t] * __builtin_amdgcn_rcpf(scur[t]);  // powers of two: exact
+                if (f != 1.0f) scale_b(b[t], f);
+            }
+        } else if (F::SCALED) {
             chg_n = in_.srow != ic.srow || in_.sidx != ic.sidx || in_.fac != ic.fac;
 #pragma unroll
             for (int t = 0; t < NT; ++t) sn[t] = chg_n ? scale_of(in_, t) * in_.fac : sc[t];
@@ -365,15 +402,18 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
     load_a(a1, 1);
     load_a(a2, 2);
     load_a(a3, 3);
-    for (int st = 0; st < nsteps; st += 4) {
+    // whole groups of four steps without exits (the wait counts stay exact),
+    // then the remaining ones
+    int st = 0;
+    for (; st + 4 <= nsteps; st += 4) {
         step(a0, b0, b1, st);
-        if (st + 1 >= nsteps) break;
         step(a1, b1, b0, st + 1);
-        if (st + 2 >= nsteps) break;
         step(a2, b0, b1, st + 2);
-        if (st + 3 >= nsteps) break;
         step(a3, b1, b0, st + 3);
     }
+    if (st < nsteps) step(a0, b0, b1, st);
+    if (st + 1 < nsteps) step(a1, b1, b0, st + 1);
+    if (st + 2 < nsteps) step(a2, b0, b1, st + 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,8 +520,16 @@ __device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
     const int64_t b0 = cload(p.chunks, u.c0).xoff;
     int nsteps = 0;
     for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
-    float sv = 1.0f;  // lane j: n-tile scale of the unit's chunk j
-    if (LANE_SCALES && F::SCALED && lane < u.nc) sv = p.sx[(int64_t)(u.c0 + lane) * p.ntmax];
+    float sv[NT];  // lane j: n-tile scales of the unit's chunk j
+    int vn = 0;    // lane j: K-blocks of the unit's chunk j
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sv[t] = 1.0f;
+    if (LANE_SCALES && lane < u.nc) {
+        vn = p.chunks[u.c0 + lane].nkb;
+        if (F::SCALED)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sv[t] = p.sx[(int64_t)(u.c0 + lane) * p.ntmax + t];
+    }
     h2 vl[4];  // FP8 forms: lo-scale of the lane's V column in each m-subtile, twice
     if constexpr (F::FP8) {
 #pragma unroll
@@ -503,12 +551,12 @@ __device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
     auto info = [&](int st) {
         while (st >= cend) {
             ++c;
-            cend += cload(p.chunks, c).nkb;
+            cend += LANE_SCALES ? __builtin_amdgcn_readlane(vn, c - u.c0) : cload(p.chunks, c).nkb;
         }
         return StepInfo{(b0 + (int64_t)st * ntm) * bbytes, LANE_SCALES ? nullptr : p.sx + (int64_t)c * ntm, 1.0f,
                         LANE_SCALES ? c - u.c0 : 0, 0, 0};
     };
-    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, prep, acc, scur, sv);
+    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, prep, acc, scur, sv, u.nc);
     float *out = p.part + u.poff;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -579,6 +627,34 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     }
 }
 
+// A chunk's step table held one entry per lane: lane l has the B offset (KiB)
+// and the segment of step w0 + l; the following 64 steps are loaded when a
+// window is entered and taken over when the next one is, so a step never
+// waits on a load issued in it (a wait there would also drain the prefetched
+// fragments). advance() is called with steps that grow by at most one.
+struct StepWindow {
+    int w0 = 0, bkib = 0, seg = 0, nb = 0, ns = 0;
+    __device__ static inline int at(int st, int nsteps) { return st < nsteps ? st : nsteps - 1; }
+    __device__ inline void init(const MRStep *steps, int nsteps, int lane) {
+        const MRStep e = steps[at(lane, nsteps)];
+        const MRStep f = steps[at(64 + lane, nsteps)];
+        bkib = (int)(e.bofs >> 10);
+        seg = e.lseg;
+        nb = (int)(f.bofs >> 10);
+        ns = f.lseg;
+    }
+    __device__ inline void advance(const MRStep *steps, int nsteps, int lane, int st) {
+        if (st >= w0 + 64) {
+            w0 += 64;
+            bkib = nb;
+            seg = ns;
+            const MRStep f = steps[at(w0 + 64 + lane, nsteps)];
+            nb = (int)(f.bofs >> 10);
+            ns = f.lseg;
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Target side, one wave per row tile (<= 64 rows of one target leaf): Y over
 // the z of every ancestor block and over x of every source leaf, written once.
@@ -602,10 +678,23 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
     // table gives each step's B fragment (z of a block, or x of a source leaf).
     const MRStep *steps = p.ustep + ch.step_base;
     const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;  // this target leaf's dense scales
-    float sv = 1.0f;  // lane j: n-tile scale of the chunk's segment j
-    if (LANE_SCALES && F::SCALED && lane < ch.nseg) {
-        const MRSeg sg = p.segs[ch.seg_base + lane];  // per lane: a vector load
-        sv = sg.kind == 0 ? p.sz[(int64_t)sg.sidx * p.ntmax] : p.sx[(int64_t)sg.sidx * p.ntmax];
+    // LANE_SCALES (at most 64 segments): per lane j, segment j's n-tile scales,
+    // its dense factor and kind; per lane l, step w0 + l of a window of 64
+    // steps (its B offset in KiB and its segment). A step then reads them with
+    // readlane: no scalar memory access on its path.
+    float sv[NT];
+    float fv = 1.0f;
+    int vk = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sv[t] = 1.0f;
+    if (LANE_SCALES && lane < ch.nseg) {
+        const MRSeg sg = p.segs[ch.seg_base + lane];  // per lane: vector loads
+        const float *row = (sg.kind == 0 ? p.sz : p.sx) + (int64_t)sg.sidx * p.ntmax;
+        vk = sg.kind;
+        if (sg.kind == 1) fv = drow[sg.leaf];
+        if (F::SCALED)  // the segment's scales with its dense factor folded in
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sv[t] = row[t] * fv;
     }
     if constexpr (F::FP8) {  // the chunk's U lo-scales, 32 per z step, into this wave's LDS table
         const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
@@ -613,11 +702,21 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
     }
+    // LANE_SCALES: the step table one entry per lane, 64 steps at a time, the
+    // next 64 loaded a window ahead (so that using them waits for no recent load)
+    StepWindow win;
+    if constexpr (LANE_SCALES) win.init(steps, ch.nsteps, lane);
     auto info = [&](int st) {
-        const MRStep e = cload(steps, st);
-        return StepInfo{e.bofs, LANE_SCALES ? nullptr : p.scales + (int64_t)e.srow * p.ntmax,
-                        e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f, LANE_SCALES ? e.lseg : 0, e.sleaf >= 0 ? 1 : 0,
-                        st * 32};
+        if constexpr (LANE_SCALES) {
+            win.advance(steps, ch.nsteps, lane, st);
+            const int seg = __builtin_amdgcn_readlane(win.seg, st - win.w0);
+            return StepInfo{(int64_t)__builtin_amdgcn_readlane(win.bkib, st - win.w0) << 10, nullptr, 1.0f, seg,
+                            __builtin_amdgcn_readlane(vk, seg), st * 32};
+        } else {
+            const MRStep e = cload(steps, st);
+            return StepInfo{e.bofs, p.scales + (int64_t)e.srow * p.ntmax, e.sleaf >= 0 ? sload(drow, e.sleaf) : 1.0f,
+                            0, e.sleaf >= 0 ? 1 : 0, st * 32};
+        }
     };
     auto prep = [&](const typename F::A &a, int, const StepInfo &si) -> typename F::Op {
         if constexpr (F::FP8) {
@@ -630,7 +729,193 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
             return a;
         }
     };
-    mfma_steps<STORE, NT, LANE_SCALES>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, prep, acc, scur, sv);
+    mfma_steps<STORE, NT, LANE_SCALES>(p.UD, p.zpack, tl.aoff, nm, ch.nsteps, lane, info, prep, acc, scur, sv,
+                                       ch.nseg);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = t * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * m + 4 * (lane >> 4) + i;
+                if (m < nm && row < tl.rows && n < k) {
+                    float *yp = y + (int64_t)(tl.row0 + row) + (int64_t)n * ldy;
+                    float v = alpha * (acc[m][t][i] * scur[t]);
+                    if (beta != 0.0f) v = fmaf(beta, *yp, v);
+                    *yp = v;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Target side, one workgroup of four waves per tile group (up to four row
+// tiles of one chunk). The tiles of a chunk multiply the same sequence of B
+// fragments, so B is staged once per step in LDS for the workgroup instead of
+// being read by every wave: two LDS slots (step s reads slot s & 1 while B of
+// step s + 1 is written to the other), one barrier per step, and B of step
+// s + 3 loaded into registers (two staging sets) two steps before it is
+// written. Each wave streams its own A as in mr_tile. A wave without a tile
+// takes part in the staging and the barriers only, so every wave of the
+// workgroup passes the same barriers. The step table and the scales are held
+// one per lane (at most 64 segments per chunk), read with readlane.
+// ring: 2 x NT x 16 x BFRAG bytes of LDS; stab: the chunk's step table (nsteps
+// entries); lo_lds (FP8 forms): 16 x nzsteps words per wave.
+// ---------------------------------------------------------------------------
+template <int STORE, int NT>
+__device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alpha, float beta,
+                                     float *__restrict__ y, int64_t ldy, unsigned char *ring, int2 *stab,
+                                     uint32_t *lo_lds) {
+    using F = MR<STORE>;
+    constexpr int kUnits = NT * F::BFRAG;  // 16-byte pieces of one step's B
+    constexpr int kSlot = kUnits * 16;
+    constexpr int kPer = (kUnits + 255) / 256;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const MRTileGroup tg = cload(p.tgroups, g);
+    const bool active = wave < tg.ntiles;
+    const MRTile tl = cload(p.tiles, tg.tile0 + (active ? wave : 0));
+    const MRChunk ch = cload(p.chunks, tg.chunk);
+    const int nm = tl.nm, nsteps = ch.nsteps;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
+    float scur[NT], sv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
+    const MRStep *steps = p.ustep + ch.step_base;
+    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;
+    float fv = 1.0f;
+    int vk = 0;
+    if (lane < ch.nseg) {  // per lane j: segment j's n-tile scales, dense factor and kind
+        const MRSeg sg = p.segs[ch.seg_base + lane];
+        const float *row = (sg.kind == 0 ? p.sz : p.sx) + (int64_t)sg.sidx * p.ntmax;
+        vk = sg.kind;
+        if (sg.kind == 1) fv = drow[sg.leaf];
+        if (F::SCALED)  // the segment's scales with its dense factor folded in
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sv[t] = row[t] * fv;
+    }
+    if (F::SCALED)  // one common scale per n-tile: the largest of the tile's (see mfma_steps)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, ch.nseg);
+    if constexpr (F::FP8) {  // the chunk's U lo-scales, into this wave's LDS table
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
+        for (int i = lane; i < ch.nzsteps * 16; i += 64) lo_lds[i] = src[i];
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+    }
+    // the chunk's step table (B offset in KiB, segment) copied into LDS once, so
+    // that no step waits on a global load other than its fragments'
+    for (int i = tid; i < nsteps; i += 256) {
+        const MRStep e = steps[i];
+        stab[i] = int2{(int)(e.bofs >> 10), e.lseg};
+    }
+    __syncthreads();
+    auto clamp = [&](int st) { return st < nsteps ? st : nsteps - 1; };
+    auto bofs_of = [&](int st) -> int64_t { return (int64_t)__builtin_amdgcn_readfirstlane(stab[st].x) << 10; };
+    auto info = [&](int st) {
+        const int seg = __builtin_amdgcn_readfirstlane(stab[st].y);
+        return StepInfo{0, nullptr, 1.0f, seg, __builtin_amdgcn_readlane(vk, seg), st * 32};
+    };
+    auto scale_of = [&](const StepInfo &i, int t) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv[t]), i.sidx));
+    };
+    auto prep = [&](const typename F::A &a, const StepInfo &si) -> typename F::Op {
+        if constexpr (F::FP8) {
+            if (si.dense) return F::dense(a);
+            const h2 *q = reinterpret_cast<const h2 *>(lo_lds) + (si.lofs + 8 * (lane >> 4)) / 2;
+            const h2 s2[4] = {q[0], q[1], q[2], q[3]};
+            return F::hilo(a, s2);
+        } else {
+            return a;
+        }
+    };
+    const rsrc_t ra = make_rsrc(static_cast<const char *>(p.UD) + tl.aoff * 1024);
+    typename F::A a0[4], a1[4], a2[4], a3[4];
+    u32x4 g0[kPer], g1[kPer];
+    // (a wave without a tile loads the first tile's fragments too, unused:
+    // with every load unconditional the wait counts stay exact)
+    auto load_a = [&](typename F::A(&a)[4], int st) {
+        const int sc = clamp(st);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
+    };
+    auto gload = [&](u32x4(&gs)[kPer], int st) {  // this thread's pieces of B(st), clamped to the last step
+        const rsrc_t rb = make_rsrc(static_cast<const char *>(p.zpack) + bofs_of(clamp(st)));
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int u = tid + 256 * i;
+            gs[i] = __builtin_bit_cast(
+                u32x4, buf16<0>(rb, (kUnits % 256 == 0 ? u : (u < kUnits ? u : kUnits - 1)) * 16, 0));
+        }
+    };
+    auto swrite = [&](const u32x4(&gs)[kPer], int slot) {
+        u32x4 *dst = reinterpret_cast<u32x4 *>(ring + slot * kSlot);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int u = tid + 256 * i;
+            if (kUnits % 256 == 0 || u < kUnits) dst[u] = gs[i];
+        }
+    };
+    StepInfo ic = info(0), in_;
+    // step st reads slot st & 1; at its start B(st + 1) goes from staging set
+    // (st + 1) & 1 into slot (st + 1) & 1, and that set is refilled with B(st + 3)
+    auto step = [&](typename F::A(&a)[4], u32x4(&gs)[kPer], int st) {
+        swrite(gs, (st + 1) & 1);
+        gload(gs, st + 3);
+        in_ = info(clamp(st + 1));
+        if (active) {
+            typename F::Op op[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) op[m] = prep(a[m], ic);
+            const unsigned char *slot = ring + (st & 1) * kSlot;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                typename F::B b;
+                if constexpr (STORE == HMAT_STORE_FP32) {
+                    b.v = *reinterpret_cast<const f32x4 *>(slot + t * 16 * F::BFRAG + lane * 16);
+                } else {
+                    b.hi = *reinterpret_cast<const decltype(b.hi) *>(slot + t * 16 * F::BFRAG + lane * 16);
+                    b.lo = *reinterpret_cast<const decltype(b.lo) *>(slot + t * 16 * F::BFRAG + 1024 + lane * 16);
+                }
+                if constexpr (F::SCALED) {  // this step's scale over the common one: a power of two <= 1
+                    const float f = scale_of(ic, t) * __builtin_amdgcn_rcpf(scur[t]);
+                    if (f != 1.0f) scale_b(b, f);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (m < nm) F::mma(op[m], b, acc[m][t]);
+            }
+        }
+        load_a(a, st + 4);
+        ic = in_;
+        __syncthreads();  // slot st & 1 is free again; B(st + 1) is visible to every wave
+    };
+    gload(g0, 0);
+    swrite(g0, 0);
+    gload(g1, 1);
+    gload(g0, 2);
+    load_a(a0, 0);
+    load_a(a1, 1);
+    load_a(a2, 2);
+    load_a(a3, 3);
+    __syncthreads();
+    // whole groups of four steps without exits, then the remaining ones
+    int st = 0;
+    for (; st + 4 <= nsteps; st += 4) {
+        step(a0, g1, st);
+        step(a1, g0, st + 1);
+        step(a2, g1, st + 2);
+        step(a3, g0, st + 3);
+    }
+    if (st < nsteps) step(a0, g1, st);
+    if (st + 1 < nsteps) step(a1, g0, st + 1);
+    if (st + 2 < nsteps) step(a2, g1, st + 2);
+    if (!active) return;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll

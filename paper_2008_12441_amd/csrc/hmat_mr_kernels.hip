@@ -35,9 +35,9 @@ __global__ __launch_bounds__(256) void k_xpack(DevPlanMR p, const float *__restr
 
 template <int STORE, int NT>
 __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_vmfma(DevPlanMR p) {
-    const int w = wave_id(4);
+    const int w = wave_id_xcd(4);
     if (w >= p.num_vunits) return;
-    mr_vunit<STORE, NT, false>(p, w, threadIdx.x & 63);
+    mr_vunit<STORE, NT, true>(p, w, threadIdx.x & 63);
 }
 
 template <int STORE>
@@ -48,14 +48,42 @@ __global__ __launch_bounds__(256) void k_zmfma(DevPlanMR p, int nt_used) {
     mr_zitem<STORE>(p, w / nt_used, w % nt_used, threadIdx.x & 63, zs[threadIdx.x >> 6]);
 }
 
-template <int STORE, int NT>
+// LS: the chunks have at most 64 target-side segments, so a tile's step table
+// and scales are held one per lane (see mfma_steps); otherwise they are read
+// through the scalar cache.
+template <int STORE, int NT, bool LS>
 __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_umfma(DevPlanMR p, int k, float alpha, float beta,
                                                                      float *__restrict__ y, int64_t ldy) {
     extern __shared__ __align__(16) uint32_t lo_tables[];  // FP8 forms: 16 x max_nzsteps words per wave
     const int w = wave_id_xcd(4);
     if (w >= p.num_tiles) return;
-    mr_tile<STORE, NT, false>(p, w, threadIdx.x & 63, k, alpha, beta, y, ldy,
-                              lo_tables + (threadIdx.x >> 6) * 16 * p.max_nzsteps);
+    mr_tile<STORE, NT, LS>(p, w, threadIdx.x & 63, k, alpha, beta, y, ldy,
+                           lo_tables + (threadIdx.x >> 6) * 16 * p.max_nzsteps);
+}
+
+// One workgroup per tile group, B shared through LDS (mr_tile_group);
+// XCD-aware numbering keeps neighbouring chunks (which share their
+// ancestors' z) in one L2.
+// waves per SIMD the group kernel is compiled for: two where its registers fit
+// in 256 without spilling (measured on the compiler's output), else one
+template <int STORE, int NT>
+struct GroupOcc {
+    static constexpr int waves = (NT <= 4 || !MR<STORE>::SCALED) ? 2 : 1;
+};
+
+template <int STORE, int NT>
+__global__ __launch_bounds__(256, (GroupOcc<STORE, NT>::waves)) void k_umfma_group(DevPlanMR p, int k, float alpha, float beta,
+                                                        float *__restrict__ y, int64_t ldy) {
+    // two B slots, the step table (max_nsteps entries), then (FP8 forms) the lo-scale tables
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b % kXcds, j = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int g = x * per + (x < rem ? x : rem) + j;
+    constexpr int kRing = 2 * NT * MR<STORE>::BFRAG * 16;
+    int2 *stab = reinterpret_cast<int2 *>(smem + kRing);
+    mr_tile_group<STORE, NT>(p, g, k, alpha, beta, y, ldy, smem, stab,
+                             reinterpret_cast<uint32_t *>(stab + p.max_nsteps) + (threadIdx.x >> 6) * 16 * p.max_nzsteps);
 }
 
 template <int STORE, int NT>
@@ -76,8 +104,16 @@ int launch_mr_nt(const DevPlanMR &p, int32_t k, float alpha, const float *x, int
     }
     if (mark) mark(ctx, 2);
     const size_t lds = IsFp8<STORE>::value ? (size_t)4 * 64 * p.max_nzsteps : 0;
-    hipLaunchKernelGGL((k_umfma<STORE, NT>), dim3((p.num_tiles + 3) / 4), dim3(256), lds, st, p, k, alpha, beta, y,
-                       ldy);
+    const size_t glds = (size_t)2 * NT * MR<STORE>::BFRAG * 16 + (size_t)8 * p.max_nsteps + lds;
+    if (p.max_nseg <= 64 && glds <= 65536)
+        hipLaunchKernelGGL((k_umfma_group<STORE, NT>), dim3(p.num_tgroups), dim3(256), glds, st, p, k, alpha, beta, y,
+                           ldy);
+    else if (p.max_nseg <= 64)
+        hipLaunchKernelGGL((k_umfma<STORE, NT, true>), dim3((p.num_tiles + 3) / 4), dim3(256), lds, st, p, k, alpha,
+                           beta, y, ldy);
+    else
+        hipLaunchKernelGGL((k_umfma<STORE, NT, false>), dim3((p.num_tiles + 3) / 4), dim3(256), lds, st, p, k, alpha,
+                           beta, y, ldy);
     if ((e = (int)hipGetLastError())) return e;
     if (mark) mark(ctx, 3);
     return 0;
