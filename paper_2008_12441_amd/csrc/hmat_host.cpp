@@ -1289,7 +1289,9 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.max_nzsteps = 0;
     p.max_nseg = 0;
     p.max_nsteps = 0;
+    p.max_chunk_rows = 0;
     for (const hmat::MRChunk &c : hp.chunks) {
+        p.max_chunk_rows = std::max(p.max_chunk_rows, c.rows);
         p.max_nzsteps = std::max(p.max_nzsteps, c.nzsteps);
         p.max_nseg = std::max(p.max_nseg, c.nseg);
         p.max_nsteps = std::max(p.max_nsteps, c.nsteps);

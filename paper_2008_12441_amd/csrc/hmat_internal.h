@@ -228,6 +228,8 @@ struct DevPlanMR {
     int32_t max_nseg;         // most target-side segments of a chunk
     int32_t num_tgroups;
     int32_t max_nsteps;       // most target-side steps of a chunk
+    int32_t max_chunk_rows;
+    int32_t pad_;
     const void *V;            // A fragments
     const void *UD;
     void *xpack;              // B fragments of X (in the same allocation as zpack, after it)

@@ -499,6 +499,69 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
 }
 
 // ---------------------------------------------------------------------------
+// The same packing for chunks of at most 512 rows, with X read coalesced: each
+// wave reads four of the 16 columns, 64 consecutive rows per instruction, into
+// an LDS tile (16 x (rows + 1) floats, the padding spreads the banks), and the
+// fragments are then assembled from LDS. Same values as mr_xpack.
+// ---------------------------------------------------------------------------
+constexpr int kXpackMaxRows = 512;
+
+template <int STORE>
+__device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx,
+                                     int k, float *tile, float *red) {
+    using F = MR<STORE>;
+    constexpr int VW = F::VW;
+    constexpr int KB = F::KB;
+    const MRChunk ch = cload(p.chunks, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rs = ch.rows + 1;  // LDS row stride of a column
+    float m = 0.0f;
+    float v[4][kXpackMaxRows / 64];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // all loads first: 32 in flight per thread
+        const int n = nt * 16 + 4 * wave + j;
+        const float *col = x + (int64_t)n * ldx + ch.row_begin;
+#pragma unroll
+        for (int i = 0; i < kXpackMaxRows / 64; ++i) {
+            const int r = lane + 64 * i;
+            v[j][i] = (n < k && r < ch.rows) ? col[r] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < kXpackMaxRows / 64; ++i) {
+            const int r = lane + 64 * i;
+            if (r < ch.rows) tile[(4 * wave + j) * rs + r] = v[j][i];
+            m = fmaxf(m, fabsf(v[j][i]));
+        }
+    float inv = 1.0f;
+    if (F::SCALED) {
+        m = wave_max(m);
+        if (lane == 0) red[wave] = m;
+    }
+    __syncthreads();
+    if (F::SCALED) {
+        const float sc = col_scale(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+        if (tid == 0) p.sx[(int64_t)c * p.ntmax + nt] = sc;
+        inv = 1.0f / sc;
+    }
+    const int j = lane & 15;
+    for (int kb = wave; kb < ch.nkb; kb += 4) {
+        int lf = 0;  // the leaf holding K-block kb (leaves start on K-block boundaries)
+        while (lf + 1 < ch.nleaf && cload(p.leaves, ch.leaf_base + lf + 1).kb0 <= kb) ++lf;
+        const MRLeaf L = cload(p.leaves, ch.leaf_base + lf);
+        const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
+        const float *src = tile + j * rs + (L.row_begin - ch.row_begin);
+        float t[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) t[e] = off0 + e < L.rows ? src[off0 + e] * inv : 0.0f;
+        F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, t);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Source side, one wave per unit; acc[m-subtile][n-tile] are 16x16 tiles.
 // ---------------------------------------------------------------------------
 template <int STORE, int NT, bool LANE_SCALES>

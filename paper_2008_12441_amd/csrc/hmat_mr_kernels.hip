@@ -33,6 +33,15 @@ __global__ __launch_bounds__(256) void k_xpack(DevPlanMR p, const float *__restr
     mr_xpack<STORE>(p, blockIdx.x / nt_used, blockIdx.x % nt_used, x, ldx, k, red);
 }
 
+// chunks of at most kXpackMaxRows rows: X read coalesced through an LDS tile
+template <int STORE>
+__global__ __launch_bounds__(256) void k_xpack_tile(DevPlanMR p, const float *__restrict__ x, int64_t ldx, int k) {
+    extern __shared__ __align__(16) float xtile[];  // 16 x (max chunk rows + 1), then 4 maxima
+    const int nt_used = (k + 15) / 16;
+    mr_xpack_tile<STORE>(p, blockIdx.x / nt_used, blockIdx.x % nt_used, x, ldx, k, xtile,
+                         xtile + 16 * (p.max_chunk_rows + 1));
+}
+
 template <int STORE, int NT>
 __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_vmfma(DevPlanMR p) {
     const int w = wave_id_xcd(4);
@@ -90,7 +99,11 @@ template <int STORE, int NT>
 int launch_mr_nt(const DevPlanMR &p, int32_t k, float alpha, const float *x, int64_t ldx, float beta, float *y,
                  int64_t ldy, hipStream_t st, void (*mark)(void *, int), void *ctx) {
     if (mark) mark(ctx, 0);
-    hipLaunchKernelGGL(k_xpack<STORE>, dim3(p.num_chunks * NT), dim3(256), 0, st, p, x, ldx, k);
+    if (p.max_chunk_rows <= kXpackMaxRows)
+        hipLaunchKernelGGL(k_xpack_tile<STORE>, dim3(p.num_chunks * NT), dim3(256),
+                           (size_t)(16 * (p.max_chunk_rows + 1) + 4) * 4, st, p, x, ldx, k);
+    else
+        hipLaunchKernelGGL(k_xpack<STORE>, dim3(p.num_chunks * NT), dim3(256), 0, st, p, x, ldx, k);
     int e = (int)hipGetLastError();
     if (e) return e;
     if (p.num_vunits > 0) {
