@@ -760,6 +760,7 @@ struct HostPlanMR {
     std::vector<int32_t> seg_node;             // source leaf node of an x segment
     std::vector<hmat::MRTile> tiles;
     std::vector<hmat::MRTileGroup> tgroups;
+    std::vector<hmat::MRUnitGroup> ugroups;
     std::vector<hmat::MRStep> ustep;
     std::vector<float> dscale;
     std::vector<std::vector<std::pair<int64_t, int32_t>>> colmap;  // per node s: V column -> (block, j)
@@ -932,6 +933,15 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         hp.vunits.swap(vu);
         hp.unit_node.swap(un);
         hp.unit_group.swap(ug);
+    }
+    // unit groups: up to four consecutive units over the same chunks (they share their X fragments)
+    for (int32_t i = 0; i < (int32_t)hp.vunits.size();) {
+        int32_t j = i + 1;
+        while (j < (int32_t)hp.vunits.size() && j - i < 4 && hp.vunits[j].c0 == hp.vunits[i].c0 &&
+               hp.vunits[j].nc == hp.vunits[i].nc)
+            ++j;
+        hp.ugroups.push_back(hmat::MRUnitGroup{i, j - i});
+        i = j;
     }
     // z items: one per low-rank block
     std::vector<int32_t> zitem_of(nb, -1);
@@ -1254,6 +1264,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tgroups, &p.tgroups)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.ugroups, &p.ugroups)) != HMAT_OK) return s;
     if ((s = upload(h, hp.ustep, &p.ustep)) != HMAT_OK) return s;
     if (hp.fp8) {
         if ((s = upload(h, hp.vlo, &p.vlo)) != HMAT_OK) return s;
@@ -1286,6 +1297,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.num_zitems = (int32_t)hp.zitems.size();
     p.num_tiles = (int32_t)hp.tiles.size();
     p.num_tgroups = (int32_t)hp.tgroups.size();
+    p.num_ugroups = (int32_t)hp.ugroups.size();
     p.max_nzsteps = 0;
     p.max_nseg = 0;
     p.max_nsteps = 0;

@@ -209,6 +209,11 @@ struct MRTileGroup {      // up to four consecutive row tiles of one chunk, run 
     int32_t pad_;
 };
 
+struct MRUnitGroup {      // up to four consecutive V units over the same chunks, run by one workgroup
+    int32_t u0;
+    int32_t count;
+};
+
 struct MRStep {           // one K-block step of a chunk's target-side contraction
     int64_t bofs;         // byte offset of its B fragments from zpack (xpack follows zpack)
     int32_t srow;         // row of its n-tile scales in the scale array (z rows, then x rows)
@@ -229,7 +234,7 @@ struct DevPlanMR {
     int32_t num_tgroups;
     int32_t max_nsteps;       // most target-side steps of a chunk
     int32_t max_chunk_rows;
-    int32_t pad_;
+    int32_t num_ugroups;
     const void *V;            // A fragments
     const void *UD;
     void *xpack;              // B fragments of X (in the same allocation as zpack, after it)
@@ -245,6 +250,7 @@ struct DevPlanMR {
     const MRSeg *segs;
     const MRTile *tiles;
     const MRTileGroup *tgroups;
+    const MRUnitGroup *ugroups;
     const MRStep *ustep;      // per chunk step (MRChunk::step_base)
     const float *scales;      // n-tile scales: sz rows (one per z item), then sx rows (one per chunk)
     // FP8 forms

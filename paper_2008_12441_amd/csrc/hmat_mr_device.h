@@ -813,102 +813,43 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
 }
 
 // ---------------------------------------------------------------------------
-// Target side, one workgroup of four waves per tile group (up to four row
-// tiles of one chunk). The tiles of a chunk multiply the same sequence of B
-// fragments, so B is staged once per step in LDS for the workgroup instead of
-// being read by every wave: two LDS slots (step s reads slot s & 1 while B of
-// step s + 1 is written to the other), one barrier per step, and B of step
-// s + 3 loaded into registers (two staging sets) two steps before it is
-// written. Each wave streams its own A as in mr_tile. A wave without a tile
-// takes part in the staging and the barriers only, so every wave of the
-// workgroup passes the same barriers. The step table and the scales are held
-// one per lane (at most 64 segments per chunk), read with readlane.
-// ring: 2 x NT x 16 x BFRAG bytes of LDS; stab: the chunk's step table (nsteps
-// entries); lo_lds (FP8 forms): 16 x nzsteps words per wave.
+// The step loop of a workgroup of four waves that multiply one sequence of B
+// fragments, each with its own A (row tiles of one chunk, or V units over the
+// same chunks). B of every step is staged once in LDS for the workgroup
+// instead of being read by every wave: two LDS slots (step s reads slot s & 1
+// while B of step s + 1 is written to the other), one barrier per step, and B
+// of step s + 3 loaded into registers (two staging sets) two steps before it
+// is written. A wave without work (active false) takes part in the staging and
+// the barriers, and loads some valid A it does not use: with every load
+// unconditional and no exits inside a group of four steps, the wait counts
+// stay exact and prefetched fragments are never drained.
+// The scales are the common-scale scheme of mfma_steps: scur[t] is the n-tile's
+// common scale, sv[t] (lane j) the scale of the j-th entry info(s).sidx points at.
+// ring: 2 x NT x 16 x BFRAG bytes of LDS.
 // ---------------------------------------------------------------------------
-template <int STORE, int NT>
-__device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alpha, float beta,
-                                     float *__restrict__ y, int64_t ldy, unsigned char *ring, int2 *stab,
-                                     uint32_t *lo_lds) {
+template <int STORE, int NT, class BOfs, class Info, class Prep>
+__device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, const void *B, int nsteps, bool active,
+                                        int tid, unsigned char *ring, BOfs bofs_of, Info info, Prep prep,
+                                        f32x4 (&acc)[4][NT], const float (&scur)[NT], const float (&sv)[NT]) {
     using F = MR<STORE>;
     constexpr int kUnits = NT * F::BFRAG;  // 16-byte pieces of one step's B
     constexpr int kSlot = kUnits * 16;
     constexpr int kPer = (kUnits + 255) / 256;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const MRTileGroup tg = cload(p.tgroups, g);
-    const bool active = wave < tg.ntiles;
-    const MRTile tl = cload(p.tiles, tg.tile0 + (active ? wave : 0));
-    const MRChunk ch = cload(p.chunks, tg.chunk);
-    const int nm = tl.nm, nsteps = ch.nsteps;
-    f32x4 acc[4][NT];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
-    float scur[NT], sv[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
-    const MRStep *steps = p.ustep + ch.step_base;
-    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;
-    float fv = 1.0f;
-    int vk = 0;
-    if (lane < ch.nseg) {  // per lane j: segment j's n-tile scales, dense factor and kind
-        const MRSeg sg = p.segs[ch.seg_base + lane];
-        const float *row = (sg.kind == 0 ? p.sz : p.sx) + (int64_t)sg.sidx * p.ntmax;
-        vk = sg.kind;
-        if (sg.kind == 1) fv = drow[sg.leaf];
-        if (F::SCALED)  // the segment's scales with its dense factor folded in
-#pragma unroll
-            for (int t = 0; t < NT; ++t) sv[t] = row[t] * fv;
-    }
-    if (F::SCALED)  // one common scale per n-tile: the largest of the tile's (see mfma_steps)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, ch.nseg);
-    if constexpr (F::FP8) {  // the chunk's U lo-scales, into this wave's LDS table
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
-        for (int i = lane; i < ch.nzsteps * 16; i += 64) lo_lds[i] = src[i];
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-    }
-    // the chunk's step table (B offset in KiB, segment) copied into LDS once, so
-    // that no step waits on a global load other than its fragments'
-    for (int i = tid; i < nsteps; i += 256) {
-        const MRStep e = steps[i];
-        stab[i] = int2{(int)(e.bofs >> 10), e.lseg};
-    }
-    __syncthreads();
+    const int lane = tid & 63;
     auto clamp = [&](int st) { return st < nsteps ? st : nsteps - 1; };
-    auto bofs_of = [&](int st) -> int64_t { return (int64_t)__builtin_amdgcn_readfirstlane(stab[st].x) << 10; };
-    auto info = [&](int st) {
-        const int seg = __builtin_amdgcn_readfirstlane(stab[st].y);
-        return StepInfo{0, nullptr, 1.0f, seg, __builtin_amdgcn_readlane(vk, seg), st * 32};
-    };
     auto scale_of = [&](const StepInfo &i, int t) {
         return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv[t]), i.sidx));
     };
-    auto prep = [&](const typename F::A &a, const StepInfo &si) -> typename F::Op {
-        if constexpr (F::FP8) {
-            if (si.dense) return F::dense(a);
-            const h2 *q = reinterpret_cast<const h2 *>(lo_lds) + (si.lofs + 8 * (lane >> 4)) / 2;
-            const h2 s2[4] = {q[0], q[1], q[2], q[3]};
-            return F::hilo(a, s2);
-        } else {
-            return a;
-        }
-    };
-    const rsrc_t ra = make_rsrc(static_cast<const char *>(p.UD) + tl.aoff * 1024);
+    const rsrc_t ra = make_rsrc(static_cast<const char *>(A) + af0 * 1024);
     typename F::A a0[4], a1[4], a2[4], a3[4];
     u32x4 g0[kPer], g1[kPer];
-    // (a wave without a tile loads the first tile's fragments too, unused:
-    // with every load unconditional the wait counts stay exact)
     auto load_a = [&](typename F::A(&a)[4], int st) {
         const int sc = clamp(st);
 #pragma unroll
         for (int m = 0; m < 4; ++m) a[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
     };
     auto gload = [&](u32x4(&gs)[kPer], int st) {  // this thread's pieces of B(st), clamped to the last step
-        const rsrc_t rb = make_rsrc(static_cast<const char *>(p.zpack) + bofs_of(clamp(st)));
+        const rsrc_t rb = make_rsrc(static_cast<const char *>(B) + bofs_of(clamp(st)));
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int u = tid + 256 * i;
@@ -925,8 +866,6 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
         }
     };
     StepInfo ic = info(0), in_;
-    // step st reads slot st & 1; at its start B(st + 1) goes from staging set
-    // (st + 1) & 1 into slot (st + 1) & 1, and that set is refilled with B(st + 3)
     auto step = [&](typename F::A(&a)[4], u32x4(&gs)[kPer], int st) {
         swrite(gs, (st + 1) & 1);
         gload(gs, st + 3);
@@ -934,7 +873,7 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
         if (active) {
             typename F::Op op[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) op[m] = prep(a[m], ic);
+            for (int m = 0; m < 4; ++m) op[m] = prep(a[m], m, ic);
             const unsigned char *slot = ring + (st & 1) * kSlot;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -967,8 +906,7 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
     load_a(a2, 2);
     load_a(a3, 3);
     __syncthreads();
-    // whole groups of four steps without exits, then the remaining ones
-    int st = 0;
+    int st = 0;  // whole groups of four steps without exits, then the remaining ones
     for (; st + 4 <= nsteps; st += 4) {
         step(a0, g1, st);
         step(a1, g0, st + 1);
@@ -978,6 +916,80 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
     if (st < nsteps) step(a0, g1, st);
     if (st + 1 < nsteps) step(a1, g0, st + 1);
     if (st + 2 < nsteps) step(a2, g1, st + 2);
+}
+
+// ---------------------------------------------------------------------------
+// Target side, one workgroup of four waves per tile group (up to four row
+// tiles of one chunk, which multiply the same B sequence): mfma_steps_group
+// over the chunk's step table, copied into LDS once so that no step waits on
+// a global load other than its fragments. The segment scales are held one per
+// lane (at most 64 segments per chunk).
+// stab: nsteps entries of LDS; lo_lds (FP8 forms): 16 x nzsteps words per wave.
+// ---------------------------------------------------------------------------
+template <int STORE, int NT>
+__device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alpha, float beta,
+                                     float *__restrict__ y, int64_t ldy, unsigned char *ring, int2 *stab,
+                                     uint32_t *lo_lds) {
+    using F = MR<STORE>;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const MRTileGroup tg = cload(p.tgroups, g);
+    const bool active = wave < tg.ntiles;
+    const MRTile tl = cload(p.tiles, tg.tile0 + (active ? wave : 0));
+    const MRChunk ch = cload(p.chunks, tg.chunk);
+    const int nm = tl.nm, nsteps = ch.nsteps;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
+    float scur[NT], sv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
+    const MRStep *steps = p.ustep + ch.step_base;
+    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;
+    float fv = 1.0f;
+    int vk = 0;
+    if (lane < ch.nseg) {  // per lane j: segment j's n-tile scales (dense factor folded in) and kind
+        const MRSeg sg = p.segs[ch.seg_base + lane];
+        const float *row = (sg.kind == 0 ? p.sz : p.sx) + (int64_t)sg.sidx * p.ntmax;
+        vk = sg.kind;
+        if (sg.kind == 1) fv = drow[sg.leaf];
+        if (F::SCALED)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sv[t] = row[t] * fv;
+    }
+    if (F::SCALED)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, ch.nseg);
+    if constexpr (F::FP8) {  // the chunk's U lo-scales, into this wave's LDS table
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
+        for (int i = lane; i < ch.nzsteps * 16; i += 64) lo_lds[i] = src[i];
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int i = tid; i < nsteps; i += 256) {  // step table: B offset in KiB, segment
+        const MRStep e = steps[i];
+        stab[i] = int2{(int)(e.bofs >> 10), e.lseg};
+    }
+    __syncthreads();
+    auto bofs_of = [&](int st) -> int64_t { return (int64_t)__builtin_amdgcn_readfirstlane(stab[st].x) << 10; };
+    auto info = [&](int st) {
+        const int seg = __builtin_amdgcn_readfirstlane(stab[st].y);
+        return StepInfo{0, nullptr, 1.0f, seg, __builtin_amdgcn_readlane(vk, seg), st * 32};
+    };
+    auto prep = [&](const typename F::A &a, int, const StepInfo &si) -> typename F::Op {
+        if constexpr (F::FP8) {
+            if (si.dense) return F::dense(a);
+            const h2 *q = reinterpret_cast<const h2 *>(lo_lds) + (si.lofs + 8 * (lane >> 4)) / 2;
+            const h2 s2[4] = {q[0], q[1], q[2], q[3]};
+            return F::hilo(a, s2);
+        } else {
+            return a;
+        }
+    };
+    mfma_steps_group<STORE, NT>(p.UD, tl.aoff, nm, p.zpack, nsteps, active, tid, ring, bofs_of, info, prep, acc,
+                                scur, sv);
     if (!active) return;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -995,6 +1007,81 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
                 }
             }
         }
+}
+
+// ---------------------------------------------------------------------------
+// Source side, one workgroup of four waves per unit group (up to four V units
+// over the same chunks, which multiply the same X fragments): mfma_steps_group
+// with the X fragments of the chunks as B. Same partial sums as mr_vunit.
+// ---------------------------------------------------------------------------
+template <int STORE, int NT>
+__device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *ring) {
+    using F = MR<STORE>;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const MRUnitGroup ug = cload(p.ugroups, g);
+    const bool active = wave < ug.count;
+    const MRVUnit u = cload(p.vunits, ug.u0 + (active ? wave : 0));
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
+    float scur[NT], sv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
+    int nsteps = 0;
+    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
+    int vn = 0;  // lane j: K-blocks of the unit's chunk j
+    if (lane < u.nc) {
+        vn = p.chunks[u.c0 + lane].nkb;
+        if (F::SCALED)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) sv[t] = p.sx[(int64_t)(u.c0 + lane) * p.ntmax + t];
+    }
+    if (F::SCALED)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, u.nc);
+    h2 vl[4];  // FP8 forms: lo-scale of the lane's V column in each m-subtile, twice
+    if constexpr (F::FP8) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const _Float16 sl = __builtin_bit_cast(_Float16, p.vlo[(int64_t)u.lo_off * 64 + 16 * m + (lane & 15)]);
+            vl[m] = h2{sl, sl};
+        }
+    }
+    auto prep = [&](const typename F::A &a, int m, const StepInfo &) -> typename F::Op {
+        if constexpr (F::FP8) {
+            const h2 s2[4] = {vl[m], vl[m], vl[m], vl[m]};
+            return F::hilo(a, s2);
+        } else {
+            return a;
+        }
+    };
+    const int64_t b0 = cload(p.chunks, u.c0).xoff, ntm = p.ntmax;
+    constexpr int64_t bbytes = 16 * F::BFRAG;
+    auto bofs_of = [&](int st) -> int64_t { return (b0 + (int64_t)st * ntm) * bbytes; };
+    int c = 0, cend = 0;  // chunk (index in the unit) of the step asked for last, and the step where it ends
+    cend = __builtin_amdgcn_readlane(vn, 0);
+    auto info = [&](int st) {
+        while (st >= cend) {
+            ++c;
+            cend += __builtin_amdgcn_readlane(vn, c);
+        }
+        return StepInfo{0, nullptr, 1.0f, c, 0, 0};
+    };
+    mfma_steps_group<STORE, NT>(p.V, u.aoff, u.nm, p.xpack, nsteps, active, tid, ring, bofs_of, info, prep, acc,
+                                scur, sv);
+    if (!active) return;
+    const int ncol = p.ntmax * 16;
+    float *out = p.part + u.poff;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[(int64_t)(16 * m + 4 * (lane >> 4) + i) * ncol + t * 16 + (lane & 15)] = acc[m][t][i] * scur[t];
 }
 
 }  // namespace dev

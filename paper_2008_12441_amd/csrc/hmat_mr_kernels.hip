@@ -42,6 +42,23 @@ __global__ __launch_bounds__(256) void k_xpack_tile(DevPlanMR p, const float *__
                          xtile + 16 * (p.max_chunk_rows + 1));
 }
 
+// waves per SIMD the group kernels are compiled for: two where their registers
+// fit in 256 without spilling (measured on the compiler's output), else one
+template <int STORE, int NT>
+struct GroupOcc {
+    static constexpr int waves = (NT <= 4 || !MR<STORE>::SCALED) ? 2 : 1;
+};
+
+// one workgroup per unit group, X fragments shared through LDS (mr_vunit_group)
+template <int STORE, int NT>
+__global__ __launch_bounds__(256, (GroupOcc<STORE, NT>::waves)) void k_vmfma_group(DevPlanMR p) {
+    extern __shared__ __align__(16) unsigned char vring[];  // two B slots
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b % kXcds, j = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    mr_vunit_group<STORE, NT>(p, x * per + (x < rem ? x : rem) + j, vring);
+}
+
 template <int STORE, int NT>
 __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_vmfma(DevPlanMR p) {
     const int w = wave_id_xcd(4);
@@ -73,12 +90,6 @@ __global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_umfma(DevPlanMR p
 // One workgroup per tile group, B shared through LDS (mr_tile_group);
 // XCD-aware numbering keeps neighbouring chunks (which share their
 // ancestors' z) in one L2.
-// waves per SIMD the group kernel is compiled for: two where its registers fit
-// in 256 without spilling (measured on the compiler's output), else one
-template <int STORE, int NT>
-struct GroupOcc {
-    static constexpr int waves = (NT <= 4 || !MR<STORE>::SCALED) ? 2 : 1;
-};
 
 template <int STORE, int NT>
 __global__ __launch_bounds__(256, (GroupOcc<STORE, NT>::waves)) void k_umfma_group(DevPlanMR p, int k, float alpha, float beta,
@@ -107,7 +118,8 @@ int launch_mr_nt(const DevPlanMR &p, int32_t k, float alpha, const float *x, int
     int e = (int)hipGetLastError();
     if (e) return e;
     if (p.num_vunits > 0) {
-        hipLaunchKernelGGL((k_vmfma<STORE, NT>), dim3((p.num_vunits + 3) / 4), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_vmfma_group<STORE, NT>), dim3(p.num_ugroups), dim3(256),
+                           (size_t)2 * NT * MR<STORE>::BFRAG * 16, st, p);
         if ((e = (int)hipGetLastError())) return e;
     }
     if (mark) mark(ctx, 1);
