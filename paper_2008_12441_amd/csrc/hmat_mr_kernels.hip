@@ -1,9 +1,13 @@
 // HIP kernels (gfx950) of the multi-RHS H-matrix-vector product on MFMA.
 //
 // Per group of at most 128 right-hand sides four launches run on the caller's
-// stream (bodies in hmat_mr_device.h): k_xpack (one workgroup per chunk and
-// n-tile), k_vmfma (one wave per V unit), k_zmfma (one wave per low-rank
-// block and n-tile) and k_umfma (one wave per row tile).
+// stream (bodies in hmat_mr_device.h): X packing (one workgroup per chunk and
+// n-tile: k_xpack_tile, or k_xpack for chunks of more than 512 rows), the
+// source side (k_vmfma_group: one workgroup per group of four V units over the
+// same chunks), z packing (k_zmfma: one wave per low-rank block and n-tile)
+// and the target side (k_umfma_group: one workgroup per group of four row
+// tiles of a chunk; k_umfma, one wave per row tile, where a chunk's segments
+// or LDS needs exceed what the group kernel holds).
 #include "hmat_mr_device.h"
 
 namespace hmat {
@@ -57,13 +61,6 @@ __global__ __launch_bounds__(256, (GroupOcc<STORE, NT>::waves)) void k_vmfma_gro
     const int x = b % kXcds, j = b / kXcds;
     const int per = nb / kXcds, rem = nb % kXcds;
     mr_vunit_group<STORE, NT>(p, x * per + (x < rem ? x : rem) + j, vring);
-}
-
-template <int STORE, int NT>
-__global__ __launch_bounds__(256, Occupancy<NT>::waves) void k_vmfma(DevPlanMR p) {
-    const int w = wave_id_xcd(4);
-    if (w >= p.num_vunits) return;
-    mr_vunit<STORE, NT, true>(p, w, threadIdx.x & 63);
 }
 
 template <int STORE>
