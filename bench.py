@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-s2", action="store_true", help="skip the standard-admissibility 2D (1024^2, r=4) leg")
     ap.add_argument("--no-s3", action="store_true", help="skip the standard-admissibility 3D (64^3, r=4) leg")
     ap.add_argument("--s-steps", type=int, default=20)
+    ap.add_argument("--no-transpose", action="store_true", help="skip the transpose-product timing on c2")
     return ap.parse_args()
 
 
@@ -511,16 +512,18 @@ def main():
         y16 = None
 
     # the transpose product of the same matrix (a handle built for K^T, same kernels)
-    t0 = time.time()
-    ht = hm.HMatrix(tree, blocks, storage="fp32", transpose=True)
-    log(f"hmat_create fp32 transpose: {time.time() - t0:.1f} s")
-    ytd = torch.empty_like(xd)
-    mst, pht = time_matvecs(ht, xd, ytd, args.steps, args.warmup, stream)
-    out_extra["transpose_fp32"] = {"ms_per_step": round(mst, 5), "GBps": round(alg_bytes / (mst * 1e-3) / 1e9, 1),
-                                   "phases_ms": [round(v, 5) for v in pht]}
-    log(f"fp32 transpose: {mst:.4f} ms/matvec, {out_extra['transpose_fp32']['GBps']} GB/s")
-    ht.close()
-    del ytd
+    if not args.no_transpose:
+        t0 = time.time()
+        ht = hm.HMatrix(tree, blocks, storage="fp32", transpose=True)
+        log(f"hmat_create fp32 transpose: {time.time() - t0:.1f} s")
+        ytd = torch.empty_like(xd)
+        mst, pht = time_matvecs(ht, xd, ytd, args.steps, args.warmup, stream)
+        out_extra["transpose_fp32"] = {"ms_per_step": round(mst, 5),
+                                       "GBps": round(alg_bytes / (mst * 1e-3) / 1e9, 1),
+                                       "phases_ms": [round(v, 5) for v in pht]}
+        log(f"fp32 transpose: {mst:.4f} ms/matvec, {out_extra['transpose_fp32']['GBps']} GB/s")
+        ht.close()
+        del ytd
 
     cpu = None
     if not args.no_cpu_baseline:
