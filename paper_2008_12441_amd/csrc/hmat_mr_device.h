@@ -19,6 +19,8 @@
 
 #include "hmat_device_common.h"
 
+#include <type_traits>
+
 namespace hmat {
 namespace dev {
 
@@ -827,11 +829,32 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
 // common scale, sv[t] (lane j) the scale of the j-th entry info(s).sidx points at.
 // ring: 2 x NT x 16 x BFRAG bytes of LDS.
 // ---------------------------------------------------------------------------
+// Calls f(integral_constant<int, j>) for j = 0 .. N-1 (unrolled, j a constant).
+template <int N, class Fn, int J = 0>
+__device__ inline void static_for(Fn &&f) {
+    if constexpr (J < N) {
+        f(std::integral_constant<int, J>{});
+        static_for<N, Fn, J + 1>(static_cast<Fn &&>(f));
+    }
+}
+
+// Prefetch depths of the group step loop: KA steps of A fragments in
+// registers, KS staging sets for B. The 16-bit forms at NT > 4 use three and
+// one, which keeps them within 256 registers (two waves per SIMD).
+template <int STORE, int NT>
+struct GroupDepth {
+    static constexpr bool lean = STORE != HMAT_STORE_FP32 && NT > 4;
+    static constexpr int KA = lean ? 3 : 4;
+    static constexpr int KS = lean ? 1 : 2;
+};
+
 template <int STORE, int NT, class BOfs, class Info, class Prep>
 __device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, const void *B, int nsteps, bool active,
                                         int tid, unsigned char *ring, BOfs bofs_of, Info info, Prep prep,
                                         f32x4 (&acc)[4][NT], const float (&scur)[NT], const float (&sv)[NT]) {
     using F = MR<STORE>;
+    constexpr int KA = GroupDepth<STORE, NT>::KA, KS = GroupDepth<STORE, NT>::KS;
+    constexpr int U = KA * KS / (KA % 2 == 0 && KS == 2 ? 2 : 1);  // lcm(KA, KS) for KS in {1, 2}
     constexpr int kUnits = NT * F::BFRAG;  // 16-byte pieces of one step's B
     constexpr int kSlot = kUnits * 16;
     constexpr int kPer = (kUnits + 255) / 256;
@@ -841,12 +864,12 @@ __device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, cons
         return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sv[t]), i.sidx));
     };
     const rsrc_t ra = make_rsrc(static_cast<const char *>(A) + af0 * 1024);
-    typename F::A a0[4], a1[4], a2[4], a3[4];
-    u32x4 g0[kPer], g1[kPer];
-    auto load_a = [&](typename F::A(&a)[4], int st) {
+    typename F::A a[KA][4];
+    u32x4 g[KS][kPer];
+    auto load_a = [&](typename F::A(&as)[4], int st) {
         const int sc = clamp(st);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
+        for (int m = 0; m < 4; ++m) as[m] = F::loadA(ra, (sc * nm + (m < nm ? m : nm - 1)) * 1024, lane);
     };
     auto gload = [&](u32x4(&gs)[kPer], int st) {  // this thread's pieces of B(st), clamped to the last step
         const rsrc_t rb = make_rsrc(static_cast<const char *>(B) + bofs_of(clamp(st)));
@@ -866,14 +889,17 @@ __device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, cons
         }
     };
     StepInfo ic = info(0), in_;
-    auto step = [&](typename F::A(&a)[4], u32x4(&gs)[kPer], int st) {
-        swrite(gs, (st + 1) & 1);
-        gload(gs, st + 3);
+    // step st: A from set st % KA, B from slot st & 1; B(st + 1) goes from staging
+    // set (st + 1) % KS into the other slot, and the set is refilled with B(st + 1 + KS)
+    auto step = [&](auto JA, auto JG, int st) {
+        constexpr int ja = decltype(JA)::value, jg = decltype(JG)::value;
+        swrite(g[jg], (st + 1) & 1);
+        gload(g[jg], st + 1 + KS);
         in_ = info(clamp(st + 1));
         if (active) {
             typename F::Op op[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) op[m] = prep(a[m], m, ic);
+            for (int m = 0; m < 4; ++m) op[m] = prep(a[ja][m], m, ic);
             const unsigned char *slot = ring + (st & 1) * kSlot;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -893,29 +919,26 @@ __device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, cons
                     if (m < nm) F::mma(op[m], b, acc[m][t]);
             }
         }
-        load_a(a, st + 4);
+        load_a(a[ja], st + KA);
         ic = in_;
         __syncthreads();  // slot st & 1 is free again; B(st + 1) is visible to every wave
     };
-    gload(g0, 0);
-    swrite(g0, 0);
-    gload(g1, 1);
-    gload(g0, 2);
-    load_a(a0, 0);
-    load_a(a1, 1);
-    load_a(a2, 2);
-    load_a(a3, 3);
+    gload(g[0], 0);
+    swrite(g[0], 0);
+    static_for<KS>([&](auto J) { gload(g[(decltype(J)::value + 1) % KS], decltype(J)::value + 1); });
+    static_for<KA>([&](auto J) { load_a(a[decltype(J)::value], decltype(J)::value); });
     __syncthreads();
-    int st = 0;  // whole groups of four steps without exits, then the remaining ones
-    for (; st + 4 <= nsteps; st += 4) {
-        step(a0, g1, st);
-        step(a1, g0, st + 1);
-        step(a2, g1, st + 2);
-        step(a3, g0, st + 3);
-    }
-    if (st < nsteps) step(a0, g1, st);
-    if (st + 1 < nsteps) step(a1, g0, st + 1);
-    if (st + 2 < nsteps) step(a2, g1, st + 2);
+    int st = 0;  // whole groups of U steps without exits, then the remaining ones
+    for (; st + U <= nsteps; st += U)
+        static_for<U>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            step(std::integral_constant<int, j % KA>{}, std::integral_constant<int, (j + 1) % KS>{}, st + j);
+        });
+    static_for<U - 1>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if (st + j < nsteps)
+            step(std::integral_constant<int, j % KA>{}, std::integral_constant<int, (j + 1) % KS>{}, st + j);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -961,7 +984,9 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
     }
     if (F::SCALED)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, ch.nseg);
+        for (int t = 0; t < NT; ++t)
+            scur[t] = __builtin_bit_cast(
+                float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, lanes_max(sv[t], lane, ch.nseg))));
     if constexpr (F::FP8) {  // the chunk's U lo-scales, into this wave's LDS table
         const uint32_t *src = reinterpret_cast<const uint32_t *>(p.ulo + ch.ulo_base);
         for (int i = lane; i < ch.nzsteps * 16; i += 64) lo_lds[i] = src[i];
@@ -1041,7 +1066,9 @@ __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *
     }
     if (F::SCALED)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) scur[t] = lanes_max(sv[t], lane, u.nc);
+        for (int t = 0; t < NT; ++t)
+            scur[t] = __builtin_bit_cast(
+                float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, lanes_max(sv[t], lane, u.nc))));
     h2 vl[4];  // FP8 forms: lo-scale of the lane's V column in each m-subtile, twice
     if constexpr (F::FP8) {
 #pragma unroll
