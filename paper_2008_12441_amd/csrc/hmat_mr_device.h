@@ -839,11 +839,12 @@ __device__ inline void static_for(Fn &&f) {
 }
 
 // Prefetch depths of the group step loop: KA steps of A fragments in
-// registers, KS staging sets for B. The 16-bit forms at NT > 4 use three and
-// one, which keeps them within 256 registers (two waves per SIMD).
+// registers, KS staging sets for B. The 16-bit forms from NT = 4 up use three
+// and one, which keeps them within 256 registers at NT > 4 (two waves per
+// SIMD) and within 168 at NT = 4 (three).
 template <int STORE, int NT>
 struct GroupDepth {
-    static constexpr bool lean = STORE != HMAT_STORE_FP32 && NT > 4;
+    static constexpr bool lean = STORE != HMAT_STORE_FP32 && NT >= 4;
     static constexpr int KA = lean ? 3 : 4;
     static constexpr int KS = lean ? 1 : 2;
 };

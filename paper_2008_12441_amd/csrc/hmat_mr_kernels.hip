@@ -46,11 +46,12 @@ __global__ __launch_bounds__(256) void k_xpack_tile(DevPlanMR p, const float *__
                          xtile + 16 * (p.max_chunk_rows + 1));
 }
 
-// waves per SIMD the group kernels are compiled for: two (their registers fit
-// in 256 without spilling with the prefetch depths of GroupDepth)
+// waves per SIMD the group kernels are compiled for: three up to four n-tiles,
+// two above (their registers fit without spilling with the prefetch depths of
+// GroupDepth)
 template <int STORE, int NT>
 struct GroupOcc {
-    static constexpr int waves = 2;
+    static constexpr int waves = NT <= 4 ? 3 : 2;
 };
 
 // one workgroup per unit group, X fragments shared through LDS (mr_vunit_group)
