@@ -272,3 +272,41 @@ def test_fp8_forms_need_multi_rhs_handles(small):
         st, msg = _create_status(tree, blocks, storage=form, max_nrhs=8)
         assert st not in (1, 4), msg      # valid: fails only at the device stage on a machine without a GPU
     assert _create_status(tree, blocks, storage=5)[0] == 1
+
+
+def test_standard_admissibility_structure_validation():
+    """A standard-admissibility block set (Sec. 2, Eq. (2.2)) passes validation; the
+    same set with a block removed, with a block split into its child pairs next to
+    itself, or with a block between boxes of different depths does not."""
+    d = make_hmatrix(uniform_tree(2, 256), 4, method="random", seed=2, admissibility="standard")
+    tree, blocks, keep = descriptors(d)
+    st, msg = _create_status(tree, blocks)
+    assert st in (0, 6), msg
+    t = d.tree
+    rank = d.blocks.rank
+    # missing block
+    assert _create_status(tree, blocks[1:])[0] == 3
+    # an extra block on a child pair of a low-rank block: it lies inside that block,
+    # so it is no child pair of a recursion pair
+    lr = int(np.nonzero((rank > 0) & (t.depth[d.blocks.target] == 2))[0][0])
+    ct = t.children[int(d.blocks.target[lr])][0]
+    cs = t.children[int(d.blocks.source[lr])][0]
+    extra = blocks[lr:lr + 1].copy()
+    extra["target"] = ct
+    extra["source"] = cs
+    b2 = np.concatenate([blocks, extra])
+    st, msg = _create_status(tree, b2)
+    assert st == 3 and "recursion pair" in msg, msg
+    # a block between boxes of different depths (with a V factor of the right size)
+    b3 = blocks.copy()
+    par = int(t.parent[int(d.blocks.source[lr])])
+    vbuf = np.zeros(t.size(par) * int(rank[lr]), np.float32)
+    b3["source"][lr] = par
+    b3["b"][lr] = vbuf.ctypes.data
+    b3["ldb"][lr] = t.size(par)
+    st, msg = _create_status(tree, b3)
+    assert st == 3, msg
+    # a low-rank block between two leaves (Def. 2.3 makes leaf pairs dense)
+    dn = int(np.nonzero(rank == 0)[0][0])
+    b4 = blocks.copy(); b4["rank"][dn] = 2; b4["b"][dn] = b4["a"][dn]; b4["ldb"][dn] = 64
+    assert _create_status(tree, b4)[0] == 4
