@@ -146,10 +146,14 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
         if (HAS_M && it.kind >= BK_MX) {
             const DevPlanMR p = load_plan_mr(&a.members[it.member].mp);
             if (it.kind == BK_MX) {
-                float *red = reinterpret_cast<float *>(lds);
+                float *tile = reinterpret_cast<float *>(lds);
                 for (int j = 0; j < it.count; ++j) {
-                    if (j) __syncthreads();  // red is reused
-                    mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, red);
+                    if (j) __syncthreads();  // the tile and the maxima are reused
+                    if (p.max_chunk_rows <= kXpackMaxRows)  // coalesced, through an LDS tile
+                        mr_xpack_tile<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, tile,
+                                             tile + 16 * (p.max_chunk_rows + 1));
+                    else
+                        mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, tile);
                 }
             } else if (it.kind == BK_MV) {
                 for (int j = wave; j < it.count; j += 4) mr_vunit<STORE, 1, true>(p, it.first + j, lane);
