@@ -20,7 +20,9 @@
 //
 // An item is a run of consecutive work indices of one stage of one member,
 // grouped on the host up to a byte budget (the grain): waves take its indices
-// in turn, whole-workgroup stages take them one after the other.
+// in turn, whole-workgroup stages take them one after the other. The
+// multi-RHS V products and target sides are whole-workgroup stages over unit
+// groups and tile groups (four waves sharing one B sequence through LDS).
 //
 // The multi-RHS bodies read the n-tile scales that earlier items of the same
 // launch wrote with vector loads into a register (one per lane) instead of
@@ -155,14 +157,15 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
                     else
                         mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, tile);
                 }
-            } else if (it.kind == BK_MV) {
-                for (int j = wave; j < it.count; j += 4) mr_vunit<STORE, 1, true>(p, it.first + j, lane);
+            } else if (it.kind == BK_MV) {  // unit groups, X fragments shared through the LDS ring
+                for (int j = 0; j < it.count; ++j) mr_vunit_group<STORE, 1>(p, it.first + j, lds);
             } else if (it.kind == BK_MZ) {
                 float(*zs)[16] = reinterpret_cast<float(*)[16]>(lds) + wave * a.zs_rank;
                 for (int j = wave; j < it.count; j += 4) mr_zitem<STORE>(p, it.first + j, 0, lane, zs);
-            } else {
-                for (int j = wave; j < it.count; j += 4)
-                    mr_tile<STORE, 1, true>(p, it.first + j, lane, k, ar.alpha, ar.beta, ar.y, ar.ldy, nullptr);
+            } else {  // tile groups: the ring, then the chunk's step table
+                int2 *stab = reinterpret_cast<int2 *>(lds + 2 * MR<STORE>::BFRAG * 16);
+                for (int j = 0; j < it.count; ++j)
+                    mr_tile_group<STORE, 1>(p, it.first + j, k, ar.alpha, ar.beta, ar.y, ar.ldy, lds, stab, nullptr);
             }
         }
         if (it.done >= 0) __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2

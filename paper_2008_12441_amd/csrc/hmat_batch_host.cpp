@@ -135,9 +135,9 @@ std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i, double g
         std::vector<float> xcost(p.num_chunks);
         for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2 + 16384.0f;
         const int32_t nmx = stage(hmat::BK_MX, p.num_chunks, xcost, -1, 0, c0);
-        const int32_t nmv = stage(hmat::BK_MV, p.num_vunits, h->cost_src, c0, nmx, c0 + 1);
+        const int32_t nmv = stage(hmat::BK_MV, p.num_ugroups, h->cost_src, c0, nmx, c0 + 1);
         const int32_t nmz = stage(hmat::BK_MZ, p.num_zitems, h->cost_z1, nmv ? c0 + 1 : c0, nmv ? nmv : nmx, c0 + 2);
-        stage(hmat::BK_MU, p.num_tiles, h->cost_tgt, nmz ? c0 + 2 : c0, nmz ? nmz : nmx, -1);
+        stage(hmat::BK_MU, p.num_tgroups, h->cost_tgt, nmz ? c0 + 2 : c0, nmz ? nmz : nmx, -1);
     }
     return out;
 }
@@ -298,6 +298,9 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
             const int32_t rows = h->mrp.max_chunk_rows;
             if (rows <= 512)  // X packing through an LDS tile: 16 columns of a chunk, then four maxima
                 b->lds = std::max(b->lds, (size_t)(16 * (rows + 1) + 4) * 4);
+            // group bodies: two B slots of one n-tile, then (target side) a chunk's step table
+            const size_t ring = (size_t)2 * 16 * (h->storage == HMAT_STORE_FP32 ? 64 : 128);
+            b->lds = std::max(b->lds, ring + (size_t)8 * h->mrp.max_nsteps);
         }
     }
     b->zs_rank = (b->zs_rank + 3) / 4 * 4;

@@ -21,7 +21,8 @@ struct hmat_handle {
     hmat::DevPlanMR mrp{};
     std::vector<void *> dev_allocs;
     // work estimates for schedulers: bytes streamed per source-side work index
-    // (vtile, or V unit) and per target-side work index (chunk, or row tile)
+    // (vtile, or V unit group) and per target-side work index (chunk, or row
+    // tile group)
     std::vector<float> cost_src, cost_tgt;
     std::vector<float> cost_z1, cost_z2;  // per reduction item (multi-RHS: z items in cost_z1)
     std::vector<int32_t> chunk_rows;  // rows of each chunk

@@ -1403,13 +1403,22 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 h->chunk_rows.push_back(c.rows);
                 h->max_nseg = std::max(h->max_nseg, c.nseg);
             }
-            for (const hmat::MRVUnit &u : hpm.vunits) {
-                int64_t steps = 0;
-                for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) steps += hpm.chunks[c].nkb;
-                h->cost_src.push_back((float)(steps * u.nm * 1024));
+            // per unit group and tile group: the A fragments its waves stream (the B
+            // sequence they share is read once)
+            for (const hmat::MRUnitGroup &g : hpm.ugroups) {
+                int64_t bytes = 0;
+                for (int32_t i = g.u0; i < g.u0 + g.count; ++i) {
+                    const hmat::MRVUnit &u = hpm.vunits[i];
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkb * u.nm * 1024;
+                }
+                h->cost_src.push_back((float)bytes);
             }
-            for (const hmat::MRTile &tl : hpm.tiles)
-                h->cost_tgt.push_back((float)((int64_t)hpm.chunks[tl.chunk].nsteps * tl.nm * 1024));
+            for (const hmat::MRTileGroup &g : hpm.tgroups) {
+                int64_t bytes = 0;
+                for (int32_t i = g.tile0; i < g.tile0 + g.ntiles; ++i)
+                    bytes += (int64_t)hpm.chunks[g.chunk].nsteps * hpm.tiles[i].nm * 1024;
+                h->cost_tgt.push_back((float)bytes);
+            }
             // partials read and B fragments written (one n-tile), plus a latency term: these small
             // items are bound by round trips, not bytes
             for (const hmat::MRZItem &z : hpm.zitems)

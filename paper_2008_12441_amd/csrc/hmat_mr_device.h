@@ -6,13 +6,15 @@
 // target side Y += U Z and Y += D X (Eqs. (4.6)-(4.8)):
 //   mr_xpack   X -> B fragments per chunk (FP16: hi + lo halves, one
 //              power-of-two scale per chunk and n-tile of 16 columns);
-//   mr_vunit   per unit (level, source box, 64 V columns, up to 4 chunks):
-//              partial sums of V^T X, accumulated across the unit's chunks;
+//   mr_vunit_group  per group of up to four units (a unit: level, source
+//              box, 64 V columns, up to 4 chunks): partial sums of V^T X,
+//              accumulated across the unit's chunks;
 //   mr_zitem   per low-rank block and n-tile: the fixed-order sum of its
 //              partials (Steps 2-4 collapsed), times the block's scales, packed
 //              as B fragments (FP16: with a power-of-two scale per n-tile);
-//   mr_tile    per row tile of one target leaf: Y over the z of every ancestor
-//              block and over x of every source leaf, written once.
+//   mr_tile_group, mr_tile  per group of up to four row tiles of one chunk,
+//              or per row tile: Y over the z of every ancestor block and over
+//              x of every source leaf, written once.
 // Segment scales are powers of two, so moving the accumulators from one
 // segment's scale to the next is exact.
 #pragma once
@@ -564,75 +566,6 @@ __device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const fl
 }
 
 // ---------------------------------------------------------------------------
-// Source side, one wave per unit; acc[m-subtile][n-tile] are 16x16 tiles.
-// ---------------------------------------------------------------------------
-template <int STORE, int NT, bool LANE_SCALES>
-__device__ inline void mr_vunit(const DevPlanMR &p, int w, int lane) {
-    using F = MR<STORE>;
-    const MRVUnit u = cload(p.vunits, w);
-    f32x4 acc[4][NT];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0, 0, 0, 0};
-    float scur[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) scur[t] = 1.0f;
-    const int ncol = p.ntmax * 16;
-    // The unit's A fragments are [step][m-subtile] and its chunks' X
-    // fragments [step][n-tile], both contiguous over the unit's steps.
-    constexpr int64_t bbytes = 16 * F::BFRAG;
-    const int64_t b0 = cload(p.chunks, u.c0).xoff;
-    int nsteps = 0;
-    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
-    float sv[NT];  // lane j: n-tile scales of the unit's chunk j
-    int vn = 0;    // lane j: K-blocks of the unit's chunk j
-#pragma unroll
-    for (int t = 0; t < NT; ++t) sv[t] = 1.0f;
-    if (LANE_SCALES && lane < u.nc) {
-        vn = p.chunks[u.c0 + lane].nkb;
-        if (F::SCALED)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) sv[t] = p.sx[(int64_t)(u.c0 + lane) * p.ntmax + t];
-    }
-    h2 vl[4];  // FP8 forms: lo-scale of the lane's V column in each m-subtile, twice
-    if constexpr (F::FP8) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const _Float16 sl = __builtin_bit_cast(_Float16, p.vlo[(int64_t)u.lo_off * 64 + 16 * m + (lane & 15)]);
-            vl[m] = h2{sl, sl};
-        }
-    }
-    auto prep = [&](const typename F::A &a, int m, const StepInfo &) -> typename F::Op {
-        if constexpr (F::FP8) {
-            const h2 s2[4] = {vl[m], vl[m], vl[m], vl[m]};
-            return F::hilo(a, s2);
-        } else {
-            return a;
-        }
-    };
-    int c = u.c0 - 1, cend = 0;  // chunk of the step asked for last, and the step where it ends
-    const int64_t ntm = p.ntmax;
-    auto info = [&](int st) {
-        while (st >= cend) {
-            ++c;
-            cend += LANE_SCALES ? __builtin_amdgcn_readlane(vn, c - u.c0) : cload(p.chunks, c).nkb;
-        }
-        return StepInfo{(b0 + (int64_t)st * ntm) * bbytes, LANE_SCALES ? nullptr : p.sx + (int64_t)c * ntm, 1.0f,
-                        LANE_SCALES ? c - u.c0 : 0, 0, 0};
-    };
-    mfma_steps<STORE, NT, LANE_SCALES>(p.V, p.xpack, u.aoff, u.nm, nsteps, lane, info, prep, acc, scur, sv, u.nc);
-    float *out = p.part + u.poff;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                out[(int64_t)(16 * m + 4 * (lane >> 4) + i) * ncol + t * 16 + (lane & 15)] = acc[m][t][i] * scur[t];
-}
-
-// ---------------------------------------------------------------------------
 // Partial reduction and z packing, one wave per (low-rank block, n-tile); zs
 // is the wave's LDS scratch of kMaxRankMR x 16 floats.
 // ---------------------------------------------------------------------------
@@ -1038,7 +971,8 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
 // ---------------------------------------------------------------------------
 // Source side, one workgroup of four waves per unit group (up to four V units
 // over the same chunks, which multiply the same X fragments): mfma_steps_group
-// with the X fragments of the chunks as B. Same partial sums as mr_vunit.
+// with the X fragments of the chunks as B: each wave writes its unit's 64
+// partial sums per right-hand side column.
 // ---------------------------------------------------------------------------
 template <int STORE, int NT>
 __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *ring) {
