@@ -1,0 +1,243 @@
+"""Pins of the construction oracle (oracle/compress.py) and host-side checks of hmat_compress.
+
+C1  Philox4x64-10 against numpy's own implementation (numpy.random.Philox, whose
+    first block is drawn at counter + 1), over several keys and counters, and
+    the published known answer at counter 0, key 0.
+C2  Rademacher rows: +-1 entries with the bit mapping spelled out by hand.
+C3  kernel entries: closed forms (log kernel 0 at distance 1 and 1 at distance
+    exp(-2 pi); inverse-distance kernel 1 at distance 1 / (4 pi)), symmetry, the
+    diagonal value on coinciding global indices only.
+C4  the randomized SVD reproduces a block of exact rank <= r from any sample of
+    full rank, and its singular values are split evenly (U^T U = V^T V = S).
+C5  on kernel blocks the error lies between the Eckart-Young optimum and a
+    multiple of it (Halko, Martinsson and Tropp, Theorem 10.5 gives
+    (1 + r / (p - 1))^(1/2) times the tail in expectation for Gaussian samples).
+C6  planted mistakes in a copy of the oracle fail one of the pins above.
+Host side (no GPU): every validation error of hmat_compress is reported before
+any device call and leaves the destination arrays untouched.
+"""
+import math
+import types
+
+import numpy as np
+import pytest
+
+import paper_2008_12441_amd as hm
+from hmat_inputs import build_tree, enumerate_blocks, uniform_tree
+from oracle import compress as oc
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# --- C1 ---------------------------------------------------------------------
+def test_philox_known_answer():
+    out = oc.philox4x64_10(np.zeros((1, 4), np.uint64), (0, 0))[0]
+    assert [int(v) for v in out] == [0x16554D9ECA36314C, 0xDB20FE9D672D0FDC, 0xD7E772CEE186176B,
+                                     0x7E68B68AEC7BA23B]
+
+
+@pytest.mark.parametrize("key", [(0, 0), (5, 7), (2**64 - 1, 2**64 - 1), (0x243F6A8885A308D3, 0x13198A2E03707344)])
+def test_philox_matches_numpy(key):
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        ctr = [int(v) for v in rng.integers(0, 2**63, size=4, dtype=np.uint64)]
+        ctr[0] = ctr[0] | 1  # numpy adds one to word 0 without a carry into word 1 here
+        bg = np.random.Philox(key=key[0] | (key[1] << 64), counter=[ctr[0] - 1, ctr[1], ctr[2], ctr[3]])
+        ref = [int(v) for v in bg.random_raw(4)]
+        got = oc.philox4x64_10(np.array([ctr], np.uint64), key)[0]
+        assert [int(v) for v in got] == ref
+
+
+# --- C2 ---------------------------------------------------------------------
+def test_rademacher_bits():
+    rows = np.array([0, 1, 17, 4095, 2**31 - 5])
+    om = oc.rademacher(rows, 96, 1234)
+    assert om.shape == (5, 96) and set(np.unique(om)) <= {-1.0, 1.0}
+    for i, j in enumerate(rows):
+        w = oc.philox4x64_10(np.array([[j, 0, 0, 0]], np.uint64), (1234, 0))[0]
+        for c in (0, 1, 31, 63, 64, 95):
+            bit = (int(w[c // 64]) >> (c % 64)) & 1
+            assert om[i, c] == (-1.0 if bit else 1.0)
+    big = oc.rademacher(np.arange(20000), 64, 9)
+    assert abs(big.mean()) < 0.01
+
+
+# --- C3 ---------------------------------------------------------------------
+def test_kernel_entries_closed_forms():
+    o = np.zeros((1, 2))
+    assert oc.kernel_entries(o, np.array([[1.0, 0.0]]), "log")[0, 0] == pytest.approx(0.0, abs=1e-15)
+    assert oc.kernel_entries(o, np.array([[0.0, math.exp(-2 * math.pi)]]), "log")[0, 0] == pytest.approx(1.0)
+    o3 = np.zeros((1, 3))
+    p = np.array([[0.0, 0.0, 1.0 / (4 * math.pi)]])
+    assert oc.kernel_entries(o3, p, "inv")[0, 0] == pytest.approx(1.0)
+    pts = np.random.default_rng(2).random((7, 3))
+    for kind in ("log", "inv"):
+        k = oc.block_entries(pts, 0, 7, 0, 7, kind, 0.25)
+        assert np.allclose(k, k.T) and np.all(np.diag(k) == 0.25)
+        off = oc.block_entries(pts, 0, 3, 3, 7, kind, 0.25)
+        assert not np.any(off == 0.25)
+
+
+# --- C4, C5 -----------------------------------------------------------------
+def _check_rsvd(rsvd, rademacher, kernel_entries):
+    rng = np.random.default_rng(5)
+    # exact rank 6 (non-symmetric), r = 8, l = 12
+    a = rng.standard_normal((150, 6)) @ rng.standard_normal((6, 90))
+    om = rademacher(np.arange(90), 12, 3)
+    u, v = rsvd(a, om, 8)
+    assert np.linalg.norm(u @ v.T - a) <= 1e-12 * np.linalg.norm(a)
+    s = np.linalg.svd(a, compute_uv=False)[:8]
+    assert np.allclose(u.T @ u, np.diag(s), atol=1e-10 * s[0])
+    assert np.allclose(v.T @ v, np.diag(s), atol=1e-10 * s[0])
+    # kernel blocks between separated clusters: optimum <= error <= 3 x optimum
+    for kind, d in (("log", 2), ("inv", 3)):
+        pt = rng.random((200, d)) * 0.25
+        ps = rng.random((180, d)) * 0.25 + 0.5
+        k = kernel_entries(pt, ps, kind)
+        sv = np.linalg.svd(k, compute_uv=False)
+        for r, p in ((4, 6), (8, 10)):
+            u, v = rsvd(k, rademacher(np.arange(180), r + p, 77), r)
+            err = np.linalg.norm(k - u @ v.T)
+            opt = math.sqrt(float(np.sum(sv[r:] ** 2)))
+            assert opt * (1 - 1e-9) <= err <= 3.0 * math.sqrt(1 + r / (p - 1)) * opt
+
+
+def test_rsvd_pins():
+    _check_rsvd(oc.rsvd, oc.rademacher, oc.kernel_entries)
+
+
+def test_compress_small_tree():
+    tree = uniform_tree(2, 32)  # N = 1024
+    bl = enumerate_blocks(tree, 8)
+    out = oc.compress(tree.points, tree.begin, tree.end, zip(bl.target, bl.source, bl.rank), "log", 1.0, 10, 4)
+    for (t, s, r), f in zip(zip(bl.target, bl.source, bl.rank), out):
+        k = oc.block_entries(tree.points, tree.begin[t], tree.end[t], tree.begin[s], tree.end[s], "log", 1.0)
+        if r == 0:
+            assert f[0] == "dense" and np.array_equal(f[1], k)
+        else:
+            assert f[0] == "lowrank" and f[1].shape == (k.shape[0], r) and f[2].shape == (k.shape[1], r)
+            sv = np.linalg.svd(k, compute_uv=False)
+            opt = math.sqrt(float(np.sum(sv[r:] ** 2)))
+            assert np.linalg.norm(k - f[1] @ f[2].T) <= 3.0 * opt + 1e-12 * sv[0]
+
+
+# --- C6 ---------------------------------------------------------------------
+MUTANTS = {
+    "projection_columns_reversed": ("b = q.T @ k", "b = q.T @ k[:, ::-1]"),
+    "no_orthonormalisation": ("q, _ = np.linalg.qr(y)", "q = y"),
+    "unbalanced_split": ("return (q @ ub[:, :r]) * root[None, :], vt[:r].T * root[None, :]",
+                         "return (q @ ub[:, :r]) * root[None, :] ** 2, vt[:r].T"),
+    "sign_bit_flipped": ("return np.where(bits == 1, -1.0, 1.0)", "return np.where(bits == 1, 1.0, -1.0)"),
+    "philox_key_bump_swapped": ("k0 = (k0 + _W0) & ((1 << 64) - 1)", "k0 = (k0 + _W1) & ((1 << 64) - 1)"),
+    "log_kernel_sign": ("return -np.log(dist) / (2.0 * math.pi)", "return np.log(dist) / (2.0 * math.pi)"),
+    "wrong_truncation": ("root = np.sqrt(sv[:r])", "root = np.sqrt(sv[1:r + 1])"),
+}
+
+
+def _mutant(name):
+    src = open(oc.__file__).read()
+    old, new = MUTANTS[name]
+    assert old in src, f"mutation anchor missing for {name}"
+    src = src.replace(old, new)
+    if name == "wrong_truncation":
+        src = src.replace("return (q @ ub[:, :r]) * root[None, :], vt[:r].T * root[None, :]",
+                          "return (q @ ub[:, 1:r + 1]) * root[None, :], vt[1:r + 1].T * root[None, :]")
+    mod = types.ModuleType(f"oc_{name}")
+    exec(compile(src, f"<mutant {name}>", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutants_fail_a_pin(name):
+    m = _mutant(name)
+    failed = False
+    for pin in (lambda: _check_rsvd(m.rsvd, m.rademacher, m.kernel_entries), lambda: _pin_entries(m),
+                lambda: _pin_rademacher(m), lambda: _pin_philox(m)):
+        try:
+            pin()
+        except AssertionError:
+            failed = True
+            break
+    assert failed, f"mutant {name} passes every pin"
+
+
+def _pin_entries(m):
+    o = np.zeros((1, 2))
+    assert abs(m.kernel_entries(o, np.array([[0.0, math.exp(-2 * math.pi)]]), "log")[0, 0] - 1.0) < 1e-12
+
+
+def _pin_rademacher(m):
+    w = oc.philox4x64_10(np.array([[3, 0, 0, 0]], np.uint64), (1, 0))[0]
+    om = m.rademacher(np.array([3]), 8, 1)
+    for c in range(8):
+        assert om[0, c] == (-1.0 if (int(w[0]) >> c) & 1 else 1.0)
+
+
+def _pin_philox(m):
+    bg = np.random.Philox(key=9, counter=[0, 0, 0, 0])
+    ref = [int(v) for v in bg.random_raw(4)]
+    assert [int(v) for v in m.philox4x64_10(np.array([[1, 0, 0, 0]], np.uint64), (9, 0))[0]] == ref
+
+
+# --- host-side validation of hmat_compress ----------------------------------
+def _problem(rank=8, shape=(32, 32)):
+    tree = build_tree(shape) if len(set(shape)) > 1 else uniform_tree(len(shape), shape[0])
+    bl = enumerate_blocks(tree, rank)
+    sz = tree.end - tree.begin
+    m, n = sz[bl.target], sz[bl.source]
+    r = np.minimum(bl.rank, np.minimum(m, n)).astype(np.int32)
+    count = np.where(r == 0, m * n, (m + n) * r)
+    off_a = np.concatenate([[0], np.cumsum(count)[:-1]]).astype(np.int64)
+    off_b = np.where(r == 0, -1, off_a + m * r)
+    pool = np.full(int(count.sum()), np.nan, np.float32)
+    arr, pool = hm.make_block_array(bl.target, bl.source, r, pool, off_a, off_b, m, n)
+    return tree, hm.make_tree_desc(tree.parent, tree.begin, tree.end), arr, pool
+
+
+def _call(td, pts, arr, **kw):
+    opts = dict(kernel=0, dim=pts.shape[1] if pts is not None else 2, diag=1.0, oversample=10, seed=0, device=0,
+                reserved=0)
+    opts.update(kw)
+    o = hm.binding.hmat_compress_options(**opts)
+    lib = hm.load_library()
+    import ctypes
+
+    return lib.hmat_compress(ctypes.byref(td), pts.ctypes.data if pts is not None else None,
+                             arr.ctypes.data if arr is not None else None, len(arr) if arr is not None else 0,
+                             ctypes.byref(o))
+
+
+def test_compress_validation_errors():
+    tree, td, arr, pool = _problem()
+    pts = np.ascontiguousarray(tree.points, np.float32)
+    E = hm.binding
+    cases = [
+        (dict(kernel=2), E.HMAT_ERR_INVALID_ARG),
+        (dict(dim=0), E.HMAT_ERR_INVALID_ARG),
+        (dict(dim=4), E.HMAT_ERR_INVALID_ARG),
+        (dict(oversample=-1), E.HMAT_ERR_INVALID_ARG),
+        (dict(oversample=97), E.HMAT_ERR_INVALID_ARG),
+        (dict(reserved=1), E.HMAT_ERR_INVALID_ARG),
+        (dict(diag=float("nan")), E.HMAT_ERR_INVALID_ARG),
+        (dict(oversample=90), E.HMAT_ERR_UNSUPPORTED),  # l = min(8 + 90, |t|, |s|) > 96
+    ]
+    for kw, want in cases:
+        assert _call(td, pts, arr, **kw) == want, (kw, hm.hmat_last_error())
+    assert _call(td, None, arr) == E.HMAT_ERR_INVALID_ARG
+    bad = pts.copy()
+    bad[5, 1] = np.inf
+    assert _call(td, bad, arr) == E.HMAT_ERR_INVALID_ARG
+    assert _call(td, pts, arr[1:]) in (E.HMAT_ERR_BAD_BLOCKS,)
+    lowrank = np.nonzero(arr["rank"] > 0)[0][0]
+    nob = arr.copy()
+    nob["b"][lowrank] = 0
+    assert _call(td, pts, nob) == E.HMAT_ERR_INVALID_ARG
+    assert np.all(np.isnan(pool)), "a failed call must not write the destination arrays"
+
+
+def test_compress_python_wrapper_raises():
+    tree, td, arr, pool = _problem()
+    with pytest.raises(hm.HmatError):
+        hm.hmat_compress(td, tree.points, arr, kernel="log", oversample=200)
+    with pytest.raises(KeyError):
+        hm.hmat_compress(td, tree.points, arr, kernel="gauss")
