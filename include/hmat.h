@@ -297,6 +297,59 @@ hmat_status hmat_batch_autotune(hmat_batch_t b, float alpha, const float *const 
  * stream that still uses the batch must have completed. */
 hmat_status hmat_batch_destroy(hmat_batch_t b);
 
+/* ------------------------------------------------------------------------
+ * Construction of the block factors on the GPU.
+ *
+ * The paper takes the blocks of Def. 2.3 as given and leaves how they are
+ * computed to the literature (end of Sec. 2). hmat_compress fills a block
+ * structure from the points and a kernel function of Eq. (2.1) (without
+ * quadrature weights), so that the result can be passed to hmat_create:
+ *   dense blocks: the entries K(p_i, p_j), and `diag` where the global
+ *     indices coincide;
+ *   low-rank blocks: a randomized SVD (Halko, Martinsson and Tropp, SIAM
+ *     Review 53, 2011, Algorithms 4.1 and 5.1) of the block, whose entries
+ *     are generated on the fly and never stored: Y = K Omega with
+ *     l = min(r + oversample, |t|, |s|) columns, Q an orthonormal basis of Y,
+ *     B = Q^T K, and the rank-r truncation of the SVD of B, the singular
+ *     values split evenly: U = Q W S^(1/2), V = B^T W S^(-1/2) for the leading
+ *     r left singular vectors W of B. Omega is Rademacher: entry (j, c) is +1
+ *     when bit (c mod 64) of word (c div 64) of Philox4x64-10 (Salmon et al.,
+ *     SC 2011) at counter (j, 0, 0, 0), key (seed, 0) is clear and -1 when it
+ *     is set, j the global index of the source point.
+ * Entries and sample products are FP32; the small Gram matrices and their
+ * eigen-decompositions (which give Q and W) are FP64.
+ * ------------------------------------------------------------------------ */
+#define HMAT_KERNEL_LOG 0  /* -log|x - y| / (2 pi) */
+#define HMAT_KERNEL_INV 1  /* 1 / (4 pi |x - y|) */
+
+typedef struct hmat_compress_options {
+    int32_t kernel;      /* HMAT_KERNEL_LOG or HMAT_KERNEL_INV */
+    int32_t dim;         /* coordinates per point, 1 <= dim <= 3 */
+    float diag;          /* K(p_i, p_i) */
+    int32_t oversample;  /* p, 0 <= p <= 96; every low-rank block needs l <= 96 */
+    uint64_t seed;       /* Philox key word 0 */
+    int32_t device;      /* HIP device ordinal to compute on */
+    int32_t reserved;    /* must be 0 */
+} hmat_compress_options;
+
+/* Fill the factors of every block of a Def. 2.3 block structure.
+ *
+ * tree and blocks as for hmat_create, except that the factor pointers are
+ * the destinations: a dense block's a receives the |t| x |s| entries
+ * (column-major, lda); a low-rank block's a receives U (|t| x rank, lda) and
+ * b receives V (|s| x rank, ldb). They are FP32 host arrays owned by the
+ * caller, which the call writes (a const_cast of the descriptor's pointers).
+ * points: n x dim FP32 host array, row-major, in tree order.
+ * The call is synchronous; device memory it takes is released before it
+ * returns.
+ *
+ * Errors: INVALID_ARG (null pointers, sizes, options), BAD_TREE, BAD_BLOCKS
+ * and UNSUPPORTED as for hmat_create, UNSUPPORTED also for a low-rank block
+ * whose l exceeds 96; NOMEM; DEVICE. Nothing is written on a validation
+ * error. */
+hmat_status hmat_compress(const hmat_tree_desc *tree, const float *points, const hmat_block_desc *blocks,
+                          int64_t num_blocks, const hmat_compress_options *opts);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *hmat_last_error(void);
 

@@ -35,6 +35,10 @@ HMAT_FLAG_TRANSPOSE = 2
 
 HMAT_NUM_PHASES = 3
 
+HMAT_KERNEL_LOG = 0
+HMAT_KERNEL_INV = 1
+KERNEL = {"log": HMAT_KERNEL_LOG, "inv": HMAT_KERNEL_INV}
+
 
 class hmat_tree_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("num_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -70,6 +74,12 @@ BLOCK_DTYPE = np.dtype([("target", np.int32), ("source", np.int32), ("rank", np.
                         ("b", np.uint64), ("ldb", np.int64)], align=True)
 assert BLOCK_DTYPE.itemsize == ctypes.sizeof(hmat_block_desc)
 
+class hmat_compress_options(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("dim", ctypes.c_int32), ("diag", ctypes.c_float),
+                ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class hmat_batch_options(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("spin_limit", ctypes.c_int32), ("grain_kb", ctypes.c_int32)]
@@ -91,7 +101,7 @@ class hmat_batch_info(ctypes.Structure):
 EXPORTED = ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
             "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string",
             "hmat_batch_create", "hmat_batch_matvec", "hmat_batch_sync", "hmat_batch_set_options",
-            "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy")
+            "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy", "hmat_compress")
 
 
 class HmatError(RuntimeError):
@@ -141,10 +151,11 @@ def load_library(path: str | None = None):
     lib.hmat_batch_autotune.argtypes = [vp, ctypes.c_float, pp, p64, ctypes.c_float, pp, p64, vp,
                                         ctypes.c_char_p, i32, ctypes.POINTER(hmat_batch_options)]
     lib.hmat_batch_destroy.argtypes = [vp]
+    lib.hmat_compress.argtypes = [ctypes.POINTER(hmat_tree_desc), vp, vp, i64, ctypes.POINTER(hmat_compress_options)]
     for name in ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
                  "hmat_get_timing", "hmat_probe_bandwidth", "hmat_batch_create", "hmat_batch_matvec",
                  "hmat_batch_sync", "hmat_batch_set_options", "hmat_batch_get_info", "hmat_batch_autotune",
-                 "hmat_batch_destroy"):
+                 "hmat_batch_destroy", "hmat_compress"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -292,6 +303,52 @@ class HMatrix:
             self.close()
         except Exception:
             pass
+
+
+def hmat_compress(tree_desc: hmat_tree_desc, points: np.ndarray, blocks: np.ndarray, *, kernel: str = "log",
+                  diag: float = 1.0, oversample: int = 10, seed: int = 0, device: int = 0):
+    """Fill the factor arrays that ``blocks`` (a BLOCK_DTYPE array) point to, on the GPU.
+
+    ``points``: n x dim coordinates in tree order. Dense blocks receive the
+    kernel entries, low-rank blocks U and V of a randomized SVD (include/hmat.h).
+    """
+    lib = load_library()
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    if pts.ndim != 2:
+        raise ValueError("points must be n x dim")
+    blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
+    opts = hmat_compress_options(KERNEL[kernel], pts.shape[1], float(diag), int(oversample), int(seed), int(device), 0)
+    _check(lib.hmat_compress(ctypes.byref(tree_desc), pts.ctypes.data, blocks.ctypes.data if len(blocks) else None,
+                             len(blocks), ctypes.byref(opts)))
+
+
+def compress_pool(parent, begin, end, target, source, rank, points, *, kernel: str = "log", diag: float = 1.0,
+                  oversample: int = 10, seed: int = 0, device: int = 0):
+    """Construct every block's factors on the GPU into one packed FP32 pool.
+
+    Block b: dense D (|t| x |s|) or U (|t| x r) at pool[off_a[b]], V (|s| x r)
+    at pool[off_b[b]] (-1 for dense), all column-major with ld |t| or |s|.
+    Returns (pool, off_a, off_b).
+    """
+    begin = np.asarray(begin, np.int64)
+    end = np.asarray(end, np.int64)
+    sz = end - begin
+    target = np.asarray(target, np.int32)
+    source = np.asarray(source, np.int32)
+    rank = np.asarray(rank, np.int32)
+    m = sz[target]
+    n = sz[source]
+    r = rank.astype(np.int64)
+    count = np.where(r == 0, m * n, (m + n) * r)
+    off_a = np.zeros(len(target), np.int64)
+    if len(target) > 1:
+        off_a[1:] = np.cumsum(count)[:-1]
+    off_b = np.where(r == 0, -1, off_a + m * r)
+    pool = np.empty(int(count.sum()), np.float32)
+    arr, pool = make_block_array(target, source, rank, pool, off_a, off_b, m, n)
+    tree = make_tree_desc(parent, begin, end)
+    hmat_compress(tree, points, arr, kernel=kernel, diag=diag, oversample=oversample, seed=seed, device=device)
+    return pool, off_a, off_b
 
 
 def _ptr_array(ptrs):

@@ -1510,6 +1510,216 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Construction of the block factors (hmat_compress): validation, block sets
+// bounded by a workspace budget, the launches of hmat_compress.hip, and the
+// copies into the caller's arrays.
+// ---------------------------------------------------------------------------
+struct DevMem {  // device allocations of one compress call, released on every exit
+    std::vector<void *> ptrs;
+    ~DevMem() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hmat_status alloc(size_t count, T **p) {
+        *p = nullptr;
+        if (fault_alloc_armed()) return fail(HMAT_ERR_NOMEM, "injected device allocation failure (HMAT_FAULT=alloc)");
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 256));
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            return fail(HMAT_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes: out of memory");
+        }
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ptrs.push_back(q);
+        *p = static_cast<T *>(q);
+        return HMAT_OK;
+    }
+    template <class T>
+    hmat_status upload(const std::vector<T> &v, T **p) {
+        hmat_status s = alloc(v.size(), p);
+        if (s != HMAT_OK) return s;
+        const hipError_t e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        return HMAT_OK;
+    }
+};
+
+hmat_status hip_status(int e, const char *what) {
+    if (e == 0) return HMAT_OK;
+    return fail(HMAT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
+}
+
+constexpr int64_t kCompressSetFloats = int64_t(1) << 30;  // 4 GiB of float workspace per block set
+
+int32_t sample_width(const Tree &t, const hmat_block_desc &d, int32_t oversample) {
+    return (int32_t)std::min<int64_t>({(int64_t)d.rank + oversample, t.size(d.target), t.size(d.source)});
+}
+
+hmat_status compress_dense(const Tree &t, const hmat_block_desc *bl, const std::vector<int64_t> &ids,
+                           const hmat::CKernel &ck) {
+    for (size_t i0 = 0; i0 < ids.size();) {
+        DevMem mem;
+        std::vector<hmat::CDense> db;
+        std::vector<hmat::CTile> tiles;
+        int64_t total = 0;
+        size_t i1 = i0;
+        for (; i1 < ids.size(); ++i1) {
+            const hmat_block_desc &d = bl[ids[i1]];
+            const int64_t ne = t.size(d.target) * t.size(d.source);
+            if (i1 > i0 && total + ne > kCompressSetFloats) break;
+            hmat::CDense c{t.begin[d.target], t.begin[d.source], (int32_t)t.size(d.target),
+                           (int32_t)t.size(d.source), total};
+            for (int64_t e = 0; e < ne; e += 256) tiles.push_back(hmat::CTile{(int32_t)db.size(), 0, e});
+            db.push_back(c);
+            total += ne;
+        }
+        hmat::CDense *ddb = nullptr;
+        hmat::CTile *dtl = nullptr;
+        float *out = nullptr;
+        hmat_status s;
+        if ((s = mem.upload(db, &ddb)) != HMAT_OK || (s = mem.upload(tiles, &dtl)) != HMAT_OK ||
+            (s = mem.alloc((size_t)total, &out)) != HMAT_OK)
+            return s;
+        if ((s = hip_status(hmat::launch_compress_dense(ck, ddb, dtl, (int64_t)tiles.size(), out, nullptr),
+                            "dense entries")) != HMAT_OK)
+            return s;
+        std::vector<float> host((size_t)total);
+        if ((s = hip_status(hipMemcpy(host.data(), out, (size_t)total * 4, hipMemcpyDeviceToHost), "hipMemcpy")) !=
+            HMAT_OK)
+            return s;
+        for (size_t i = i0; i < i1; ++i) {
+            const hmat_block_desc &d = bl[ids[i]];
+            const hmat::CDense &c = db[i - i0];
+            float *a = const_cast<float *>(d.a);
+            for (int32_t j = 0; j < c.ms; ++j)
+                std::memcpy(a + (int64_t)j * d.lda, host.data() + c.off + (int64_t)j * c.mt, (size_t)c.mt * 4);
+        }
+        i0 = i1;
+    }
+    return HMAT_OK;
+}
+
+hmat_status compress_lowrank(const Tree &t, const hmat_block_desc *bl, const std::vector<int64_t> &ids,
+                             const hmat::CKernel &ck, int32_t oversample, uint64_t seed) {
+    for (size_t i0 = 0; i0 < ids.size();) {
+        DevMem mem;
+        std::vector<hmat::CLowRank> lr;
+        std::vector<hmat::CTile> ttiles, stiles;
+        int64_t fl = 0, gl = 0;
+        int32_t max_ell = 1;
+        size_t i1 = i0;
+        // Y and B^T, then the transforms, then U and V (contiguous, copied back in one piece)
+        for (; i1 < ids.size(); ++i1) {
+            const hmat_block_desc &d = bl[ids[i1]];
+            const int64_t mt = t.size(d.target), ms = t.size(d.source);
+            const int32_t ell = sample_width(t, d, oversample);
+            const int64_t need = (mt + ms) * (ell + d.rank) + (int64_t)ell * std::max(ell, 2 * d.rank);
+            if (i1 > i0 && fl + need > kCompressSetFloats) break;
+            hmat::CLowRank c{};
+            c.t0 = t.begin[d.target];
+            c.s0 = t.begin[d.source];
+            c.mt = (int32_t)mt;
+            c.ms = (int32_t)ms;
+            c.ell = ell;
+            c.rank = d.rank;
+            c.yoff = fl;
+            c.boff = fl + mt * ell;
+            c.toff = c.boff + ms * ell;
+            fl = c.toff + (int64_t)ell * std::max(ell, 2 * d.rank);
+            c.goff = gl;
+            gl += (int64_t)ell * ell;
+            for (int64_t r = 0; r < mt; r += 256) ttiles.push_back(hmat::CTile{(int32_t)lr.size(), 0, r});
+            for (int64_t r = 0; r < ms; r += 256) stiles.push_back(hmat::CTile{(int32_t)lr.size(), 0, r});
+            max_ell = std::max(max_ell, ell);
+            lr.push_back(c);
+        }
+        const int64_t uv0 = fl;
+        for (hmat::CLowRank &c : lr) {
+            c.uoff = fl;
+            c.voff = fl + (int64_t)c.mt * c.rank;
+            fl = c.voff + (int64_t)c.ms * c.rank;
+        }
+        hmat::CLowRank *dlr = nullptr;
+        hmat::CTile *dtt = nullptr, *dst = nullptr;
+        float *fws = nullptr;
+        double *gram = nullptr;
+        hmat_status s;
+        if ((s = mem.upload(lr, &dlr)) != HMAT_OK || (s = mem.upload(ttiles, &dtt)) != HMAT_OK ||
+            (s = mem.upload(stiles, &dst)) != HMAT_OK || (s = mem.alloc((size_t)fl, &fws)) != HMAT_OK ||
+            (s = mem.alloc((size_t)gl, &gram)) != HMAT_OK)
+            return s;
+        hmat::CWork w{dlr, fws, gram, seed, (max_ell + 15) / 16 * 16, max_ell};
+        const int64_t nb = (int64_t)lr.size(), nt = (int64_t)ttiles.size(), ns = (int64_t)stiles.size();
+        int e = hmat::launch_compress_sample(ck, w, dtt, nt, 0, nullptr);  // Y = K Omega
+        for (int pass = 0; pass < 2 && !e; ++pass) {                       // Q: two SVQB passes over Y
+            if (!(e = hmat::launch_compress_gram(w, nb, 0, nullptr)) && !(e = hmat::launch_compress_eig(w, nb, 0, nullptr)))
+                e = hmat::launch_compress_apply(w, dtt, nt, 0, nullptr);
+        }
+        if (!e) e = hmat::launch_compress_sample(ck, w, dst, ns, 1, nullptr);  // B^T = K^T Q
+        if (!e) e = hmat::launch_compress_gram(w, nb, 1, nullptr);             // B B^T
+        if (!e) e = hmat::launch_compress_eig(w, nb, 1, nullptr);              // M_U, M_V
+        if (!e) e = hmat::launch_compress_apply(w, dtt, nt, 1, nullptr);       // U = Q M_U
+        if (!e) e = hmat::launch_compress_apply(w, dst, ns, 2, nullptr);       // V = B^T M_V
+        if ((s = hip_status(e, "compress launch")) != HMAT_OK) return s;
+        std::vector<float> host((size_t)(fl - uv0));
+        if ((s = hip_status(hipMemcpy(host.data(), fws + uv0, host.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy")) !=
+            HMAT_OK)
+            return s;
+        for (size_t i = i0; i < i1; ++i) {
+            const hmat_block_desc &d = bl[ids[i]];
+            const hmat::CLowRank &c = lr[i - i0];
+            float *a = const_cast<float *>(d.a), *b = const_cast<float *>(d.b);
+            for (int32_t j = 0; j < c.rank; ++j) {
+                std::memcpy(a + (int64_t)j * d.lda, host.data() + (c.uoff - uv0) + (int64_t)j * c.mt, (size_t)c.mt * 4);
+                std::memcpy(b + (int64_t)j * d.ldb, host.data() + (c.voff - uv0) + (int64_t)j * c.ms, (size_t)c.ms * 4);
+            }
+        }
+        i0 = i1;
+    }
+    return HMAT_OK;
+}
+
+hmat_status compress_impl(const hmat_tree_desc *tree, const float *points, const hmat_block_desc *blocks,
+                          int64_t nb, const hmat_compress_options *opts) {
+    if (!opts) return fail(HMAT_ERR_INVALID_ARG, "options pointer is NULL");
+    if (!points) return fail(HMAT_ERR_INVALID_ARG, "points pointer is NULL");
+    if (opts->reserved != 0) return fail(HMAT_ERR_INVALID_ARG, "options reserved field must be 0");
+    if (opts->kernel != HMAT_KERNEL_LOG && opts->kernel != HMAT_KERNEL_INV)
+        return fail(HMAT_ERR_INVALID_ARG, "unknown kernel function");
+    if (opts->dim < 1 || opts->dim > 3) return fail(HMAT_ERR_INVALID_ARG, "dim must be in [1, 3]");
+    if (!std::isfinite(opts->diag)) return fail(HMAT_ERR_INVALID_ARG, "diag must be finite");
+    if (opts->oversample < 0 || opts->oversample > hmat::kCompressMaxL)
+        return fail(HMAT_ERR_INVALID_ARG, "oversample must be in [0, 96]");
+    Tree t;
+    hmat_status s = analyse_tree(tree, t);
+    if (s != HMAT_OK) return s;
+    Structure st;
+    if ((s = validate_blocks(t, blocks, nb, st)) != HMAT_OK) return s;
+    std::vector<int64_t> dense, lowrank;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (blocks[b].rank == 0) {
+            dense.push_back(b);
+            continue;
+        }
+        if (sample_width(t, blocks[b], opts->oversample) > hmat::kCompressMaxL)
+            return fail(HMAT_ERR_UNSUPPORTED, "block " + std::to_string(b) + ": min(rank + oversample, |t|, |s|) exceeds 96");
+        lowrank.push_back(b);
+    }
+    for (int64_t i = 0; i < t.n * opts->dim; ++i)
+        if (!std::isfinite(points[i])) return fail(HMAT_ERR_INVALID_ARG, "points must be finite");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opts->device < 0 || opts->device >= ndev)
+        return fail(HMAT_ERR_INVALID_ARG, "device ordinal out of range");
+    if ((s = hip_status(hipSetDevice(opts->device), "hipSetDevice")) != HMAT_OK) return s;
+    DevMem mem;
+    float *dpts = nullptr;
+    if ((s = mem.upload(std::vector<float>(points, points + t.n * opts->dim), &dpts)) != HMAT_OK) return s;
+    const hmat::CKernel ck{dpts, opts->dim, opts->kernel, opts->diag, 0};
+    if ((s = compress_dense(t, blocks, dense, ck)) != HMAT_OK) return s;
+    return compress_lowrank(t, blocks, lowrank, ck, opts->oversample, opts->seed);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1555,6 +1765,18 @@ hmat_status hmat_create(const hmat_tree_desc *tree, const hmat_block_desc *block
     }
     *out = h;
     return HMAT_OK;
+}
+
+hmat_status hmat_compress(const hmat_tree_desc *tree, const float *points, const hmat_block_desc *blocks,
+                          int64_t num_blocks, const hmat_compress_options *opts) {
+    t_err.clear();
+    try {
+        return compress_impl(tree, points, blocks, num_blocks, opts);
+    } catch (const std::bad_alloc &) {
+        return fail(HMAT_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(HMAT_ERR_INVALID_ARG, std::string("internal error: ") + e.what());
+    }
 }
 
 hmat_status hmat_destroy(hmat_t h) {
