@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-s3", action="store_true", help="skip the standard-admissibility 3D (64^3, r=4) leg")
     ap.add_argument("--s-steps", type=int, default=20)
     ap.add_argument("--no-transpose", action="store_true", help="skip the transpose-product timing on c2")
+    ap.add_argument("--no-compress", action="store_true",
+                    help="skip the timing of the GPU construction of the factors (hmat_compress) for c2 and c3")
     return ap.parse_args()
 
 
@@ -434,6 +436,37 @@ def run_standard(stream, name, steps, warmup, with_oracle=True):
     return out
 
 
+def run_compress(name, reps=2):
+    """Wall time of hmat_compress (every block of the workload's structure: dense
+    entries and randomized SVDs on the GPU, factors copied to host memory)."""
+    import paper_2008_12441_amd as hm
+    from hmat_inputs import WORKLOADS, enumerate_blocks, uniform_tree
+
+    w = WORKLOADS[name]
+    tree = uniform_tree(w.d, w.n_axis)
+    bl = enumerate_blocks(tree, w.rank, w.admissibility)
+    sz = (tree.end - tree.begin).astype(np.int64)
+    lr = bl.rank > 0
+    lr_entries = int(np.sum(sz[bl.target[lr]] * sz[bl.source[lr]]))
+    dense_entries = int(np.sum(sz[bl.target[~lr]] * sz[bl.source[~lr]]))
+    times = []
+    for rep in range(reps):
+        t0 = time.perf_counter()
+        pool, _, _ = hm.compress_pool(tree.parent, tree.begin, tree.end, bl.target, bl.source, bl.rank, tree.points,
+                                      kernel=w.kind, diag=1.0, oversample=10, seed=w.rhs_seed)
+        times.append(time.perf_counter() - t0)
+        assert np.isfinite(pool).all()
+        del pool
+    best = min(times)
+    out = {"s": round(best, 3), "all_s": [round(t, 3) for t in times], "lowrank_blocks": int(lr.sum()),
+           "dense_blocks": int((~lr).sum()), "rank": w.rank, "oversample": 10,
+           "kernel_entries_per_s": round((2 * lr_entries + dense_entries) / best, 1),
+           "note": "wall time of the synchronous call: kernel entries generated twice per low-rank block "
+                   "(sample and projection), FP64 Gram/Jacobi per block, factors copied to host memory"}
+    log(f"compress {name}: {best:.2f} s ({out['lowrank_blocks']} low-rank, {out['dense_blocks']} dense blocks)")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -620,6 +653,14 @@ def main():
         torch.cuda.empty_cache()
         result["batched_c4"] = run_batched(stream, args.c4_steps, 3, count=args.c4_members, method=args.c4_method,
                                            with_oracle=not args.no_cpu_baseline)
+    if not args.no_compress:
+        import gc
+
+        import torch
+
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["compress"] = {name: run_compress(name) for name in ("c2", "c3")}
     print(json.dumps(result), flush=True)
 
 
