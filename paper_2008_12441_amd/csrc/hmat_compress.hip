@@ -22,7 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hmat.h"
-#include "hmat_internal.h"
+#include "hmat_compress.h"
 
 namespace hmat {
 namespace {

@@ -3,6 +3,7 @@
 // timing. The C ABI is declared in include/hmat.h.
 #include "hmat.h"
 #include "hmat_handle.h"
+#include "hmat_compress.h"
 #include "hmat_internal.h"
 
 #include <hip/hip_runtime_api.h>
