@@ -203,3 +203,54 @@ def test_c2_full_size_compress(c2_gpu):
     with create(data) as h:
         y = gpu_matvec(h, x)
     assert_close(y, oracle.oracle_matvec(data, x), 1e-5, 1e-4)
+
+
+def _single_block(n, d):
+    from hmat_inputs.tree import BlockList
+
+    tree = build_tree((n,) * d if d > 1 else (n,), n_full=(max(n, 8),) * d)
+    return tree, BlockList(np.array([0], np.int32), np.array([0], np.int32), np.array([0], np.int32))
+
+
+def test_compress_root_leaf_and_dense_only():
+    """A root that is a leaf (one dense block (0, 0) carrying the diagonal
+    value), and a one-level tree (dense blocks only)."""
+    _log("case compress root leaf")
+    tree, bl = _single_block(7, 2)  # 49 points, one leaf
+    assert tree.leaf_depth == 0
+    pool, off_a, _ = hm.compress_pool(tree.parent, tree.begin, tree.end, bl.target, bl.source, bl.rank, tree.points,
+                                      kernel="inv", diag=0.5, oversample=4, seed=1)
+    k = oc.block_entries(tree.points, 0, tree.n, 0, tree.n, "inv", 0.5)
+    d = pool.reshape(tree.n, tree.n).T.astype(np.float64)
+    assert np.all(np.diag(d) == 0.5)
+    assert np.max(np.abs(d - k) / np.maximum(1.0, np.abs(k))) <= 4e-6
+    _log("case compress dense only (16 x 16, four leaves)")
+    tree = uniform_tree(2, 16)
+    target, source, r = _blocks(tree, 8, "weak")
+    assert np.all(r == 0)
+    pool, off_a, _ = _gpu_compress(tree, target, source, r, "log", 10, 2)
+    _check_blocks(tree, target, source, r, "log", 10, 2, pool, off_a)
+
+
+def test_compress_full_rank_blocks_are_exact():
+    """Where rank = min(|t|, |s|) the sample spans the whole range of the block,
+    so U V^T reproduces K to FP32 accuracy whatever the truncation (a tight
+    check of the sample, orthonormalisation and projection kernels)."""
+    _log("case compress full-rank blocks")
+    tree = _tree((100, 37))  # ragged: boxes of 48 to 96 points above the leaves
+    sz = tree.end - tree.begin
+    target, source, r = _blocks(tree, 96, "weak")
+    full = (r > 0) & (r == np.minimum(sz[target], sz[source])) & (np.minimum(sz[target], sz[source]) <= 96)
+    assert full.any()
+    keep = (r == 0) | full
+    target, source, r = target, source, np.where(keep, r, np.minimum(r, 8)).astype(np.int32)
+    pool, off_a, _ = _gpu_compress(tree, target, source, r, "log", 0, 6)
+    for b in np.nonzero(full)[0]:
+        t, s, rr = int(target[b]), int(source[b]), int(r[b])
+        m, n = int(sz[t]), int(sz[s])
+        o = int(off_a[b])
+        u = pool[o:o + m * rr].reshape(rr, m).T.astype(np.float64)
+        v = pool[o + m * rr:o + (m + n) * rr].reshape(rr, n).T.astype(np.float64)
+        k = oc.block_entries(tree.points, tree.begin[t], tree.end[t], tree.begin[s], tree.end[s], "log", 1.0)
+        e = np.linalg.norm(u @ v.T - k) / np.linalg.norm(k)
+        assert e <= 2e-5, f"block {b} ({t}, {s}) |t|={m} |s|={n} r={rr}: {e:.2e}"
