@@ -3,22 +3,24 @@
 // Dense blocks are the kernel entries themselves. A low-rank block is
 // compressed by a randomized SVD whose kernel entries are generated on the fly
 // from the points and never stored:
-//   k_csample (mode 0)  Y = K_ts Omega, one thread per row of t, the source
-//                       points and their Rademacher rows staged through LDS;
+//   k_csample (mode 0)  Y = K_ts Omega on MFMA, the entries generated in the A
+//                       fragments, the source points and their Rademacher rows
+//                       staged through LDS;
 //   k_cgram, k_ceig, k_capply (twice)  Q from Y: the FP64 Gram matrix Y^T Y,
 //                       its Jacobi eigen-decomposition P D P^T, and
 //                       Y <- Y P D^(-1/2) (directions with D below a relative
 //                       floor dropped); the second pass makes the columns
 //                       orthonormal to working precision (the SVQB scheme of
 //                       Stathopoulos and Wu, SIAM J. Sci. Comput. 23, 2002);
-//   k_csample (mode 1)  B^T = K_st Q, one thread per row of s;
+//   k_csample (mode 1)  B^T = K_st Q on MFMA over the rows of s;
 //   k_cgram, k_ceig     B B^T = (B^T)^T B^T = W L W^T; the leading r pairs give
 //                       M_U = W_r L_r^(1/4) and M_V = W_r L_r^(-1/4);
 //   k_capply            U = Q M_U, V = B^T M_V, so that U V^T = Q W_r W_r^T B,
 //                       the rank-r truncation of Q B (Algorithm 5.1 of Halko,
 //                       Martinsson and Tropp).
-// Entries and sample products are FP32; Gram matrices, rotations and the
-// eigenvalue arithmetic are FP64.
+// Entries are FP32 and enter the sample products as exact three-part BF16
+// splits with FP32 accumulation; Gram matrices, rotations and the eigenvalue
+// arithmetic are FP64.
 #include <hip/hip_runtime.h>
 
 #include "hmat.h"
@@ -34,6 +36,17 @@ constexpr int kOther = 64;  // other-side points per LDS tile of the sample prod
 __device__ inline float kernel_entry(int kind, float d2) {
     constexpr float kInv4Pi = 0.0795774715459476679f;
     return kind == HMAT_KERNEL_LOG ? -logf(d2) * kInv4Pi : rsqrtf(d2) * kInv4Pi;
+}
+
+// The same from the hardware's base-2 logarithm and reciprocal square root
+// (v_log_f32, v_rsq_f32, about 1 ulp for the normal squared distances of
+// distinct points): the sample products, where the low-rank truncation error
+// dominates anyway.
+template <int KIND>
+__device__ inline float kernel_entry_hw(float d2) {
+    constexpr float kLn2Inv4Pi = 0.05515890003816573f, kInv4Pi = 0.0795774715459476679f;
+    if constexpr (KIND == HMAT_KERNEL_LOG) return -__builtin_amdgcn_logf(d2) * kLn2Inv4Pi;
+    return __builtin_amdgcn_rsqf(d2) * kInv4Pi;
 }
 
 __device__ inline void point3(const CKernel &k, int64_t i, float (&p)[3]) {
@@ -86,72 +99,141 @@ __global__ __launch_bounds__(256) void k_cdense(CKernel k, const CDense *__restr
     out[b.off + e] = v;
 }
 
-// Sample products, one thread per row: mode 0 rows of t against the source
-// points weighted by Omega, mode 1 rows of s against the target points weighted
-// by Q. The block's entries are symmetric in the two points (t and s are
-// disjoint, so no diagonal entry occurs).
-template <int LC>
-__global__ __launch_bounds__(256) void k_csample(CKernel k, CWork w, const CTile *__restrict__ tiles, int mode) {
-    __shared__ float opt[kOther][4];
-    __shared__ __align__(16) float wts[kOther][LC];
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// v = h + m + l exactly: each part carries 8 significant bits of the FP32 value
+// (the remainders v - h and (v - h) - m are exact in FP32).
+__device__ inline void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
+    h = (__bf16)v;
+    const float r = v - (float)h;
+    m = (__bf16)r;
+    l = (__bf16)(r - (float)m);
+}
+
+// Sample products on MFMA (16x16x32 BF16, FP32 accumulation): mode 0 rows of t
+// against the source points weighted by Omega, mode 1 rows of s against the
+// target points weighted by Q. A wave owns 64 rows (four 16-row tiles); a lane
+// generates the entries of its A fragments itself: row 16 m + lane % 16 of the
+// wave's rows against the 8 other points 8 (lane / 16) + e of a 32-point
+// k-step. Each entry is split into three BF16 parts (exact); Omega's +-1 is
+// exact in BF16 (three products per tile), Q is split the same way (the six
+// products of parts whose orders add up to at most 2^-16). The weights are
+// staged as B fragments in LDS, 64 other points per tile. Padding points and
+// rows copy a valid point, so every entry stays finite against zero weights.
+// The block's entries are symmetric in the two points (t and s are disjoint,
+// so no diagonal entry occurs).
+template <int NT, int MODE, int KIND>
+__global__ __launch_bounds__(256) void k_csample(CKernel k, CWork w, const CTile *__restrict__ tiles) {
+    constexpr int mode = MODE;
+    __shared__ float4 opt[kOther];
+    __shared__ bf16x8 wb[MODE == 0 ? 1 : 3][2][NT][64];  // [part][k-step][n-tile][lane]
     const CTile tl = tiles[blockIdx.x];
     const CLowRank b = w.blocks[tl.block];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = mode == 0 ? b.t0 : b.s0, oth0 = mode == 0 ? b.s0 : b.t0;
     const int nrows = mode == 0 ? b.mt : b.ms, noth = mode == 0 ? b.ms : b.mt;
-    const int r = (int)tl.first + tid;
-    const bool live = r < nrows;
-    float p[3] = {0.0f, 0.0f, 0.0f};
-    if (live) point3(k, row0 + r, p);
-    float acc[LC];
+    const int rbase = (int)tl.first + 64 * wave;
+    float p[4][3];
 #pragma unroll
-    for (int c = 0; c < LC; ++c) acc[c] = 0.0f;
+    for (int m = 0; m < 4; ++m) {
+        const int r = rbase + 16 * m + (lane & 15);
+        point3(k, row0 + (r < nrows ? r : 0), p[m]);
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const float *q = w.fws + b.yoff;
     for (int o0 = 0; o0 < noth; o0 += kOther) {
         const int nv = min(kOther, noth - o0);
         __syncthreads();  // the previous tile has been read
         if (tid < kOther) {
-            float o[3] = {0.0f, 0.0f, 0.0f};
-            if (tid < nv) point3(k, oth0 + o0 + tid, o);
-            opt[tid][0] = o[0];
-            opt[tid][1] = o[1];
-            opt[tid][2] = o[2];
+            float o[3];
+            point3(k, oth0 + o0 + (tid < nv ? tid : 0), o);
+            opt[tid] = make_float4(o[0], o[1], o[2], 0.0f);
         }
-        if (mode == 0) {
-            if (tid < kOther) {  // the Rademacher row of source point oth0 + o0 + tid
+        if constexpr (MODE == 0) {
+            if (tid < kOther) {  // the Rademacher row of other point o0 + tid, into its B-fragment slots
                 uint64_t c4[4] = {(uint64_t)(oth0 + o0 + tid), 0, 0, 0};
                 philox4x64_10(c4, w.seed, 0);
+                const int ks = tid >> 5, e = tid & 7, lhi = ((tid & 31) >> 3) * 16;
 #pragma unroll
-                for (int c = 0; c < LC; ++c)
-                    wts[tid][c] = (tid < nv && c < b.ell) ? (((c4[c >> 6] >> (c & 63)) & 1) ? -1.0f : 1.0f) : 0.0f;
+                for (int c = 0; c < NT * 16; ++c) {
+                    const float v = (tid < nv && c < b.ell) ? (((c4[c >> 6] >> (c & 63)) & 1) ? -1.0f : 1.0f) : 0.0f;
+                    reinterpret_cast<__bf16 *>(&wb[0][ks][c >> 4][lhi + (c & 15)])[e] = (__bf16)v;
+                }
             }
         } else {
-            for (int e = tid; e < kOther * LC; e += 256) {
-                const int ii = e % kOther, c = e / kOther;
-                wts[ii][c] = (ii < nv && c < b.ell) ? q[(int64_t)(o0 + ii) + (int64_t)c * b.mt] : 0.0f;
+            for (int e2 = tid; e2 < kOther * NT * 16; e2 += 256) {
+                const int j = e2 % kOther, c = e2 / kOther;
+                const float v = (j < nv && c < b.ell) ? q[(int64_t)(o0 + j) + (int64_t)c * b.mt] : 0.0f;
+                __bf16 h, mm, l;
+                split3(v, h, mm, l);
+                const int ks = j >> 5, e = j & 7, ln = ((j & 31) >> 3) * 16 + (c & 15);
+                reinterpret_cast<__bf16 *>(&wb[0][ks][c >> 4][ln])[e] = h;
+                reinterpret_cast<__bf16 *>(&wb[1][ks][c >> 4][ln])[e] = mm;
+                reinterpret_cast<__bf16 *>(&wb[2][ks][c >> 4][ln])[e] = l;
             }
         }
         __syncthreads();
-        if (live) {
-            for (int j = 0; j < nv; ++j) {
-                float d2 = 0.0f;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float d = p[a] - opt[j][a];
-                    d2 = fmaf(d, d, d2);
+        for (int ks = 0; ks < 2; ++ks) {
+            if (ks * 32 >= nv) break;
+            float4 o[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o[e] = opt[ks * 32 + 8 * (lane >> 4) + e];
+            bf16x8 ah[4], am[4], al[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float dx = p[m][0] - o[e].x, dy = p[m][1] - o[e].y, dz = p[m][2] - o[e].z;
+                    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    __bf16 h, mm, l;
+                    split3(kernel_entry_hw<KIND>(d2), h, mm, l);
+                    ah[m][e] = h;
+                    am[m][e] = mm;
+                    al[m][e] = l;
                 }
-                const float kv = kernel_entry(k.kind, d2);
 #pragma unroll
-                for (int c = 0; c < LC; ++c) acc[c] = fmaf(kv, wts[j][c], acc[c]);
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 bh = wb[0][ks][t][lane];
+                if constexpr (MODE == 0) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], bh, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh, acc[m][t], 0, 0, 0);
+                    }
+                } else {
+                    const bf16x8 bm = wb[1][ks][t][lane], bl = wb[2][ks][t][lane];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bm, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], bh, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], bm, acc[m][t], 0, 0, 0);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh, acc[m][t], 0, 0, 0);
+                    }
+                }
             }
         }
     }
-    if (live) {
-        float *out = w.fws + (mode == 0 ? b.yoff : b.boff);
+    float *out = w.fws + (mode == 0 ? b.yoff : b.boff);
 #pragma unroll
-        for (int c = 0; c < LC; ++c)
-            if (c < b.ell) out[r + (int64_t)c * nrows] = acc[c];
-    }
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = rbase + 16 * m + 4 * (lane >> 4) + e;
+                if (r < nrows && c < b.ell) out[r + (int64_t)c * nrows] = acc[m][t][e];
+            }
+        }
 }
 
 // Gram matrix A^T A in FP64 of a column-major FP32 block A (Y or B^T), one
@@ -376,9 +458,19 @@ int launch_compress_sample(const CKernel &k, const CWork &w, const CTile *tiles,
                            void *stream) {
     if (ntiles <= 0) return 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
-#define HMAT_CALL(L) hipLaunchKernelGGL(k_csample<L>, dim3((unsigned)ntiles), dim3(256), 0, st, k, w, tiles, mode)
+#define HMAT_LAUNCH(L, M, K) \
+    hipLaunchKernelGGL((k_csample<(L) / 16, M, K>), dim3((unsigned)ntiles), dim3(256), 0, st, k, w, tiles)
+#define HMAT_CALL(L)                                                          \
+    if (k.kind == HMAT_KERNEL_LOG) {                                           \
+        if (mode == 0) HMAT_LAUNCH(L, 0, HMAT_KERNEL_LOG);                     \
+        else HMAT_LAUNCH(L, 1, HMAT_KERNEL_LOG);                               \
+    } else {                                                                   \
+        if (mode == 0) HMAT_LAUNCH(L, 0, HMAT_KERNEL_INV);                     \
+        else HMAT_LAUNCH(L, 1, HMAT_KERNEL_INV);                               \
+    }
     HMAT_LC_SWITCH(w.lc, HMAT_CALL)
 #undef HMAT_CALL
+#undef HMAT_LAUNCH
     return (int)hipGetLastError();
 }
 
