@@ -470,9 +470,8 @@ def run_compress(name, reps=2):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported by this build "
-              "(the path holds the whole H-matrix on a single GPU; see DESIGN.md for how it would shard)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the whole H-matrix and its product live on a single GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
 
