@@ -316,8 +316,9 @@ hmat_status hmat_batch_destroy(hmat_batch_t b);
  *     when bit (c mod 64) of word (c div 64) of Philox4x64-10 (Salmon et al.,
  *     SC 2011) at counter (j, 0, 0, 0), key (seed, 0) is clear and -1 when it
  *     is set, j the global index of the source point.
- * Entries and sample products are FP32; the small Gram matrices and their
- * eigen-decompositions (which give Q and W) are FP64.
+ * Entries are FP32 (the sample products take them as exact three-part BF16
+ * splits on the matrix cores, with FP32 accumulation); the small Gram matrices
+ * and their eigen-decompositions (which give Q and W) are FP64.
  * ------------------------------------------------------------------------ */
 #define HMAT_KERNEL_LOG 0  /* -log|x - y| / (2 pi) */
 #define HMAT_KERNEL_INV 1  /* 1 / (4 pi |x - y|) */
