@@ -64,7 +64,8 @@ typedef enum hmat_storage {
  * parent[0] = -1 and [begin, end) = [0, n). Every other node i has
  * 0 <= parent[i] < i. The children of a node, taken in increasing node id,
  * must tile its range contiguously in that order. All leaves must sit at the
- * same depth. Arrays are host memory, read during hmat_create only. */
+ * same depth. Arrays are host memory, read during the call that takes them
+ * (hmat_create, hmat_compress) only. */
 typedef struct hmat_tree_desc {
     int64_t n;              /* number of points = rows = columns, 1 <= n < 2^31 */
     int32_t num_nodes;      /* >= 1 */
@@ -77,7 +78,8 @@ typedef struct hmat_tree_desc {
 /* One block of Def. 2.3. rank == 0: dense block, a = D_ts (|t| x |s|,
  * leading dimension lda >= |t|), b unused. rank > 0: low-rank block
  * K_ts = U V^T with a = U (|t| x rank, lda >= |t|) and b = V (|s| x rank,
- * ldb >= |s|). FP32 host memory, column-major, read during hmat_create only. */
+ * ldb >= |s|). FP32 host memory, column-major, read during hmat_create only
+ * (hmat_compress writes these arrays instead). */
 typedef struct hmat_block_desc {
     int32_t target;         /* node id t (rows) */
     int32_t source;         /* node id s (columns) */
