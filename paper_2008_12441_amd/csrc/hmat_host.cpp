@@ -14,6 +14,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -1558,7 +1560,7 @@ int32_t sample_width(const Tree &t, const hmat_block_desc &d, int32_t oversample
 }
 
 hmat_status compress_dense(const Tree &t, const hmat_block_desc *bl, const std::vector<int64_t> &ids,
-                           const hmat::CKernel &ck) {
+                           const hmat::CKernel &ck, std::function<void()> &pending) {
     for (size_t i0 = 0; i0 < ids.size();) {
         DevMem mem;
         std::vector<hmat::CDense> db;
@@ -1585,24 +1587,31 @@ hmat_status compress_dense(const Tree &t, const hmat_block_desc *bl, const std::
         if ((s = hip_status(hmat::launch_compress_dense(ck, ddb, dtl, (int64_t)tiles.size(), out, nullptr),
                             "dense entries")) != HMAT_OK)
             return s;
-        std::vector<float> host((size_t)total);
-        if ((s = hip_status(hipMemcpy(host.data(), out, (size_t)total * 4, hipMemcpyDeviceToHost), "hipMemcpy")) !=
+        pending();
+        auto host = std::make_shared<std::vector<float>>((size_t)total);
+        if ((s = hip_status(hipMemcpy(host->data(), out, (size_t)total * 4, hipMemcpyDeviceToHost), "hipMemcpy")) !=
             HMAT_OK)
             return s;
-        for (size_t i = i0; i < i1; ++i) {
-            const hmat_block_desc &d = bl[ids[i]];
-            const hmat::CDense &c = db[i - i0];
-            float *a = const_cast<float *>(d.a);
-            for (int32_t j = 0; j < c.ms; ++j)
-                std::memcpy(a + (int64_t)j * d.lda, host.data() + c.off + (int64_t)j * c.mt, (size_t)c.mt * 4);
-        }
+        pending = [bl, &ids, db = std::move(db), host, i0, i1]() {
+            for (size_t i = i0; i < i1; ++i) {
+                const hmat_block_desc &d = bl[ids[i]];
+                const hmat::CDense &c = db[i - i0];
+                float *a = const_cast<float *>(d.a);
+                for (int32_t j = 0; j < c.ms; ++j)
+                    std::memcpy(a + (int64_t)j * d.lda, host->data() + c.off + (int64_t)j * c.mt, (size_t)c.mt * 4);
+            }
+        };
         i0 = i1;
     }
     return HMAT_OK;
 }
 
+// `pending` holds the copy of the last set's results into the caller's arrays:
+// it runs once the next set's kernels are queued, so that the host copies
+// overlap the GPU work; the caller runs what is left at the end.
 hmat_status compress_lowrank(const Tree &t, const hmat_block_desc *bl, const std::vector<int64_t> &ids,
-                             const hmat::CKernel &ck, int32_t oversample, uint64_t seed) {
+                             const hmat::CKernel &ck, int32_t oversample, uint64_t seed,
+                             std::function<void()> &pending) {
     for (size_t i0 = 0; i0 < ids.size();) {
         DevMem mem;
         std::vector<hmat::CLowRank> lr;
@@ -1663,19 +1672,25 @@ hmat_status compress_lowrank(const Tree &t, const hmat_block_desc *bl, const std
         if (!e) e = hmat::launch_compress_apply(w, dtt, nt, 1, nullptr);       // U = Q M_U
         if (!e) e = hmat::launch_compress_apply(w, dst, ns, 2, nullptr);       // V = B^T M_V
         if ((s = hip_status(e, "compress launch")) != HMAT_OK) return s;
-        std::vector<float> host((size_t)(fl - uv0));
-        if ((s = hip_status(hipMemcpy(host.data(), fws + uv0, host.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy")) !=
-            HMAT_OK)
+        // the previous set's factors go to the caller's arrays while this set runs on the GPU
+        pending();
+        auto host = std::make_shared<std::vector<float>>((size_t)(fl - uv0));
+        if ((s = hip_status(hipMemcpy(host->data(), fws + uv0, host->size() * 4, hipMemcpyDeviceToHost),
+                            "hipMemcpy")) != HMAT_OK)
             return s;
-        for (size_t i = i0; i < i1; ++i) {
-            const hmat_block_desc &d = bl[ids[i]];
-            const hmat::CLowRank &c = lr[i - i0];
-            float *a = const_cast<float *>(d.a), *b = const_cast<float *>(d.b);
-            for (int32_t j = 0; j < c.rank; ++j) {
-                std::memcpy(a + (int64_t)j * d.lda, host.data() + (c.uoff - uv0) + (int64_t)j * c.mt, (size_t)c.mt * 4);
-                std::memcpy(b + (int64_t)j * d.ldb, host.data() + (c.voff - uv0) + (int64_t)j * c.ms, (size_t)c.ms * 4);
+        pending = [bl, &ids, lr = std::move(lr), host, i0, i1, uv0]() {
+            for (size_t i = i0; i < i1; ++i) {
+                const hmat_block_desc &d = bl[ids[i]];
+                const hmat::CLowRank &c = lr[i - i0];
+                float *a = const_cast<float *>(d.a), *b = const_cast<float *>(d.b);
+                for (int32_t j = 0; j < c.rank; ++j) {
+                    std::memcpy(a + (int64_t)j * d.lda, host->data() + (c.uoff - uv0) + (int64_t)j * c.mt,
+                                (size_t)c.mt * 4);
+                    std::memcpy(b + (int64_t)j * d.ldb, host->data() + (c.voff - uv0) + (int64_t)j * c.ms,
+                                (size_t)c.ms * 4);
+                }
             }
-        }
+        };
         i0 = i1;
     }
     return HMAT_OK;
@@ -1717,8 +1732,11 @@ hmat_status compress_impl(const hmat_tree_desc *tree, const float *points, const
     float *dpts = nullptr;
     if ((s = mem.upload(std::vector<float>(points, points + t.n * opts->dim), &dpts)) != HMAT_OK) return s;
     const hmat::CKernel ck{dpts, opts->dim, opts->kernel, opts->diag, 0};
-    if ((s = compress_dense(t, blocks, dense, ck)) != HMAT_OK) return s;
-    return compress_lowrank(t, blocks, lowrank, ck, opts->oversample, opts->seed);
+    std::function<void()> pending = [] {};
+    if ((s = compress_dense(t, blocks, dense, ck, pending)) != HMAT_OK) return s;
+    if ((s = compress_lowrank(t, blocks, lowrank, ck, opts->oversample, opts->seed, pending)) != HMAT_OK) return s;
+    pending();
+    return HMAT_OK;
 }
 
 }  // namespace
