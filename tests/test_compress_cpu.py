@@ -121,6 +121,26 @@ def test_compress_small_tree():
             assert np.linalg.norm(k - f[1] @ f[2].T) <= 3.0 * opt + 1e-12 * sv[0]
 
 
+def test_compress_standard_structure():
+    """Standard admissibility (2D 64^2, 1/r kernel): every low-rank block between
+    the optimum and the bound, every dense block the entries with the diagonal value."""
+    tree = uniform_tree(2, 64)  # N = 4096, low-rank blocks at level 2 only
+    bl = enumerate_blocks(tree, 4, "standard")
+    out = oc.compress(tree.points, tree.begin, tree.end, zip(bl.target, bl.source, bl.rank), "inv", 0.5, 6, 9)
+    nlow = 0
+    for (t, s, r), f in zip(zip(bl.target, bl.source, bl.rank), out):
+        k = oc.block_entries(tree.points, tree.begin[t], tree.end[t], tree.begin[s], tree.end[s], "inv", 0.5)
+        if r == 0:
+            assert np.array_equal(f[1], k)
+            continue
+        nlow += 1
+        sv = np.linalg.svd(k, compute_uv=False)
+        opt = math.sqrt(float(np.sum(sv[r:] ** 2)))
+        err = np.linalg.norm(k - f[1] @ f[2].T)
+        assert opt * (1 - 1e-9) <= err <= 3.0 * math.sqrt(1 + r / 5) * opt + 1e-12 * sv[0]
+    assert nlow > 0
+
+
 # --- C6 ---------------------------------------------------------------------
 MUTANTS = {
     "projection_columns_reversed": ("b = q.T @ k", "b = q.T @ k[:, ::-1]"),
