@@ -7,6 +7,12 @@
 //   quant_probe fp8col     int32 rows, cols, then a column-major float32
 //                          factor; out: per column s_j, s'_j (float32), then
 //                          per element its hi and lo codes
+//   quant_probe blk16      int32 mode, then one stored array (float32) as the
+//                          library quantises a whole block array: mode 0 the
+//                          FP16 form (per-array scale s, FP16 codes of v / s),
+//                          mode 1 the FP8 forms' dense rule (BF16 codes of
+//                          v / s with the same s); out: s (float32), then one
+//                          16-bit code per value
 #include "../paper_2008_12441_amd/csrc/hmat_host.cpp"
 
 #include <cstdio>
@@ -53,6 +59,22 @@ int main(int argc, char **argv) {
                 e4m3_hilo(a[i + (size_t)j * dims[0]], sc[2 * j], sc[2 * j + 1], &hl[0], &hl[1]);
                 std::fwrite(hl, 1, 2, stdout);
             }
+        return 0;
+    }
+    if (argc > 1 && std::strcmp(argv[1], "blk16") == 0) {
+        int32_t mode = 0;
+        if (std::fread(&mode, 4, 1, stdin) != 1) return 1;
+        std::vector<float> a;
+        float v;
+        while (std::fread(&v, 4, 1, stdin) == 1) a.push_back(v);
+        bool finite = true;
+        const float amax = col_major_amax(a.data(), (int64_t)a.size(), 1, (int64_t)a.size(), &finite);
+        const float sc = pow2_scale_f16(amax);
+        std::fwrite(&sc, 4, 1, stdout);
+        for (float e : a) {
+            const uint16_t c = mode == 0 ? quant16(e, 1.0f / sc, false) : f32_to_bf16_rne(e * (1.0f / sc));
+            std::fwrite(&c, 2, 1, stdout);
+        }
         return 0;
     }
     const float inv = argc > 1 ? std::strtof(argv[1], nullptr) : 1.0f;
