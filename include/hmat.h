@@ -183,6 +183,37 @@ hmat_status hmat_create(const hmat_tree_desc *tree, const hmat_block_desc *block
 hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx,
                         float beta, float *y, int64_t ldy, void *stream);
 
+/* For callers that cannot allocate device memory at call time: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * hmat_matvec_noalloc computes exactly what hmat_matvec computes, with the same
+ * kernels in the same order (bitwise the same y), but its workspace -- the
+ * partial sums of V^T x, the stage-1 slice sums and the z vectors -- lives in
+ * a static array of HMAT_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends, not in the handle's workspace. The
+ * call allocates nothing (no hipMalloc, no event, no host-side device-memory
+ * routine); its first call on a device looks the array's address up once.
+ *
+ * Limits: single-vector handles only (created with max_nrhs == 1, or with
+ * HMAT_FLAG_FP64_ACCUM); the handle's workspace_bytes (hmat_get_info), with
+ * each of its two parts rounded up to 256 bytes, must fit in
+ * HMAT_NOALLOC_SCRATCH_BYTES (the 2D N = 2^20, rank-32 matrix takes about
+ * 11.5 MB, twice that under HMAT_FLAG_FP64_ACCUM). Phase timing is not
+ * recorded.
+ *
+ * Concurrency: every call on a device shares that device's one array, and the
+ * array keeps the last call's contents (each call writes every workspace
+ * value before reading it). Calls that overlap in time on one device race,
+ * whatever their handles and streams: order them on one stream, or join the
+ * streams, as for calls on one handle.
+ *
+ * Arguments, ownership and the other errors as for hmat_matvec; UNSUPPORTED
+ * for a multi-RHS handle or a workspace beyond the scratch size; DEVICE when
+ * the scratch address cannot be obtained or a launch fails. */
+#define HMAT_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+hmat_status hmat_matvec_noalloc(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx,
+                                float beta, float *y, int64_t ldy, void *stream);
+
 /* Release the handle and its device memory. NULL is a no-op; an unknown or
  * already destroyed handle gives INVALID_ARG. Work queued on a stream that
  * still uses the handle must have completed. */

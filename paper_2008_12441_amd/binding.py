@@ -101,7 +101,8 @@ class hmat_batch_info(ctypes.Structure):
 EXPORTED = ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
             "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string",
             "hmat_batch_create", "hmat_batch_matvec", "hmat_batch_sync", "hmat_batch_set_options",
-            "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy", "hmat_compress")
+            "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy", "hmat_compress",
+            "hmat_matvec_noalloc")
 
 
 class HmatError(RuntimeError):
@@ -132,6 +133,7 @@ def load_library(path: str | None = None):
     lib.hmat_create.argtypes = [ctypes.POINTER(hmat_tree_desc), vp, i64, ctypes.POINTER(hmat_options),
                                 ctypes.POINTER(vp)]
     lib.hmat_matvec.argtypes = [vp, i32, ctypes.c_float, vp, i64, ctypes.c_float, vp, i64, vp]
+    lib.hmat_matvec_noalloc.argtypes = [vp, i32, ctypes.c_float, vp, i64, ctypes.c_float, vp, i64, vp]
     lib.hmat_destroy.argtypes = [vp]
     lib.hmat_get_info.argtypes = [vp, ctypes.POINTER(hmat_info)]
     lib.hmat_set_timing.argtypes = [vp, i32]
@@ -155,7 +157,7 @@ def load_library(path: str | None = None):
     for name in ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat_set_timing",
                  "hmat_get_timing", "hmat_probe_bandwidth", "hmat_batch_create", "hmat_batch_matvec",
                  "hmat_batch_sync", "hmat_batch_set_options", "hmat_batch_get_info", "hmat_batch_autotune",
-                 "hmat_batch_destroy", "hmat_compress"):
+                 "hmat_batch_destroy", "hmat_compress", "hmat_matvec_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -225,6 +227,16 @@ def hmat_matvec(h: int, nrhs: int, alpha: float, x_ptr: int, ldx: int, beta: flo
                 stream: int | None = None):
     _check(load_library().hmat_matvec(h, int(nrhs), float(alpha), x_ptr, int(ldx), float(beta), y_ptr,
                                       int(ldy), stream))
+
+
+def hmat_matvec_noalloc(h: int, nrhs: int, alpha: float, x_ptr: int, ldx: int, beta: float, y_ptr: int,
+                        ldy: int, stream: int | None = None):
+    """hmat_matvec with its workspace in the library's static scratch (no allocation)."""
+    _check(load_library().hmat_matvec_noalloc(h, int(nrhs), float(alpha), x_ptr, int(ldx), float(beta), y_ptr,
+                                              int(ldy), stream))
+
+
+HMAT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def hmat_destroy(h: int | None):

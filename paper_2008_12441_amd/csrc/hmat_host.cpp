@@ -1488,6 +1488,9 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
     p.lds_floats = hp.lds_floats;
     p.max_leaf_rows = hp.max_leaf_rows;
 
+    h->ws_part_bytes = hp.part_floats * acc_bytes;
+    h->ws_zg_bytes = hp.zg_floats * acc_bytes;
+    h->ws_slice_bytes = hp.slice_floats * acc_bytes;
     void *ws = nullptr;
     if ((s = dev_alloc(h, hp.part_floats * acc_bytes, &ws)) != HMAT_OK) return s;
     p.part = ws;
@@ -1841,8 +1844,9 @@ static void mark_phase(void *ctx, int) {
     if (m->err == HMAT_OK) m->err = record_event(m->h, m->st);
 }
 
-hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
-                        float *y, int64_t ldy, void *stream) {
+// Argument checks shared by the product entry points; makes the handle's device current.
+static hmat_status matvec_prologue(hmat_t h, int32_t nrhs, const float *x, int64_t ldx, const float *y,
+                                   int64_t ldy) {
     if (!h || !is_live(h)) return fail(HMAT_ERR_INVALID_ARG, "unknown handle");
     const int64_t n = h->info.n;
     if (nrhs < 1 || nrhs > h->max_nrhs) return fail(HMAT_ERR_INVALID_ARG, "nrhs out of [1, max_nrhs]");
@@ -1856,6 +1860,13 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int
         const hipError_t e = hipSetDevice(h->device);
         if (e != hipSuccess) return fail(HMAT_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     }
+    return HMAT_OK;
+}
+
+hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
+                        float *y, int64_t ldy, void *stream) {
+    const hmat_status ps = matvec_prologue(h, nrhs, x, ldx, y, ldy);
+    if (ps != HMAT_OK) return ps;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (h->mr) {
         for (int32_t c0 = 0; c0 < nrhs; c0 += 128) {
@@ -1886,6 +1897,44 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, float alpha, const float *x, int
             return fail(HMAT_ERR_DEVICE, std::string("U-phase launch: ") + hipGetErrorString((hipError_t)e));
         if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
         if (h->timing) h->timed_calls++;
+    }
+    return HMAT_OK;
+}
+
+hmat_status hmat_matvec_noalloc(hmat_t h, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
+                                float *y, int64_t ldy, void *stream) {
+    const hmat_status ps = matvec_prologue(h, nrhs, x, ldx, y, ldy);
+    if (ps != HMAT_OK) return ps;
+    if (h->mr)
+        return fail(HMAT_ERR_UNSUPPORTED,
+                    "hmat_matvec_noalloc: multi-RHS handles are not supported (create with max_nrhs = 1)");
+    auto round256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t part_bytes = round256(h->ws_part_bytes);
+    const int64_t need = part_bytes + round256(h->ws_zg_bytes + h->ws_slice_bytes);
+    if (need > HMAT_NOALLOC_SCRATCH_BYTES)
+        return fail(HMAT_ERR_UNSUPPORTED, "hmat_matvec_noalloc: the handle's workspace takes " + std::to_string(need) +
+                                              " bytes, more than the " + std::to_string(HMAT_NOALLOC_SCRATCH_BYTES) +
+                                              "-byte scratch");
+    void *base = nullptr;
+    int e = hmat::scratch_address(h->device, &base);
+    if (e != 0)
+        return fail(HMAT_ERR_DEVICE, std::string("scratch address (hipGetSymbolAddress): ") +
+                                         hipGetErrorString((hipError_t)e));
+    // the handle's plan with its workspace pointers moved into the scratch
+    DevPlan p = h->plan;
+    p.part = base;
+    p.zg = static_cast<char *>(base) + part_bytes;
+    p.slice = static_cast<char *>(p.zg) + h->ws_zg_bytes;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t c = 0; c < nrhs; ++c) {
+        const float *xc = x + c * ldx;
+        float *yc = y + c * ldy;
+        if (p.num_vtiles > 0 && (e = hmat::launch_vphase(p, xc, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("V-phase launch: ") + hipGetErrorString((hipError_t)e));
+        if (p.num_z1 > 0 && (e = hmat::launch_zfinish(p, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("z-finish launch: ") + hipGetErrorString((hipError_t)e));
+        if ((e = hmat::launch_uphase(p, xc, yc, alpha, beta, st)) != 0)
+            return fail(HMAT_ERR_DEVICE, std::string("U-phase launch: ") + hipGetErrorString((hipError_t)e));
     }
     return HMAT_OK;
 }

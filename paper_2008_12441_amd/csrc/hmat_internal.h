@@ -322,6 +322,9 @@ int launch_zfinish(const DevPlan &p, void *stream);
 int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float beta,
                   void *stream);
 int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
+// Device address of the library's static scratch array (HMAT_NOALLOC_SCRATCH_BYTES)
+// on `device`, which must be the current device; looked up once per device.
+int scratch_address(int device, void **ptr);
 int launch_mr(const DevPlanMR &p, int32_t nrhs, float alpha, const float *x, int64_t ldx, float beta,
               float *y, int64_t ldy, void *stream, void (*mark)(void *ctx, int phase), void *ctx);
 // hmat_batch.hip: clear the counters, then run the persistent kernel with

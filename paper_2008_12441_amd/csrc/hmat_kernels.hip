@@ -8,6 +8,8 @@
 // load a contiguous 1 KiB.
 #include "hmat_sv_device.h"
 
+#include <mutex>
+
 namespace hmat {
 namespace {
 
@@ -131,6 +133,34 @@ int launch_uphase(const DevPlan &p, const float *x, float *y, float alpha, float
     else
         launch_uphase_acc<float>(p, x, y, alpha, beta, (hipStream_t)stream);
     return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch of hmat_matvec_noalloc: the single-vector workspace
+// of a product (partial sums of V^T x, stage-1 slice sums, z vectors) held in
+// a static device array instead of the handle's own allocation. Every device
+// the library runs on holds its own copy until the process ends. In host code
+// the array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns on each device, fetched once per device below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HMAT_NOALLOC_SCRATCH_BYTES];
+
+int scratch_address(int device, void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return 0;
 }
 
 int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream) {
