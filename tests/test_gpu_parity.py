@@ -269,3 +269,28 @@ def test_c3_full_size_multi_rhs(c3_random, form):
     with create(data, storage=form, max_nrhs=64) as h:
         y = gpu_matvec(h, x)
     assert_close(y, ref, KERNEL_TOL[form], 10 * KERNEL_TOL[form])
+
+
+@pytest.fixture(scope="module")
+def c5_random():
+    """The 3D 128^3 structure (N = 2^21, rank 32) with random fills drawn on the
+    GPU, 128 right-hand sides, and the FP64 oracle's y over the canonical and
+    over the dequantised FP16 factors (all columns)."""
+    _log("building c5-size factor set (3D, N=128^3, rank 32, random fill) and its oracle products")
+    data = make_hmatrix(uniform_tree(3, 128), 32, kind="inv", method="random", seed=25, device="cuda")
+    x = make_rhs(data.n, 128, 1005)
+    ref = oracle.oracle_matvec(data, x)
+    ref16 = oracle.oracle_matvec(dequantised(data, "fp16"), x)
+    return data, x, ref, ref16
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16"])
+def test_c5_full_size_multi_rhs(c5_random, form):
+    """Every column of every 16-column n-tile at the 3D N = 2^21, 128-RHS size."""
+    data, x, ref, ref16 = c5_random
+    _log(f"case c5 {form} full size, 128 RHS")
+    with create(data, storage=form, max_nrhs=128) as h:
+        y = gpu_matvec(h, x)
+    assert_close(y, ref if form == "fp32" else ref16, KERNEL_TOL[form], 10 * KERNEL_TOL[form])
+    if form == "fp16":
+        assert_close(y, ref, 1e-3)
