@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -32,15 +33,18 @@ def build(verbose: bool = False) -> str:
     """Compile every source of the library and link it; always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    objs = []
+    jobs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        _run([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    # the sources compile independently; a few at a time bounds the memory the compilers take
+    workers = max(1, min(len(jobs), int(os.environ.get("HMAT_BUILD_JOBS", "4"))))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        list(pool.map(lambda j: _run(j[0], verbose), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
           "-lpthread"], verbose)
