@@ -17,8 +17,8 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
-HOST_SOURCES = ["hmat_host.cpp", "hmat_batch_host.cpp"]
-HIP_SOURCES = ["hmat_kernels.hip", "hmat_mr_kernels.hip", "hmat_batch.hip", "hmat_compress.hip"]
+HOST_SOURCES = ["hmat_host.cpp", "hmat_batch_host.cpp", "hmat_structure.cpp", "hmat_h2_host.cpp"]
+HIP_SOURCES = ["hmat_kernels.hip", "hmat_mr_kernels.hip", "hmat_batch.hip", "hmat_compress.hip", "hmat_h2.hip"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
               f"-I{ROCM}/include", f"-I{INCLUDE}", f"-I{CSRC}"]
 

@@ -102,7 +102,8 @@ EXPORTED = ("hmat_create", "hmat_matvec", "hmat_destroy", "hmat_get_info", "hmat
             "hmat_get_timing", "hmat_probe_bandwidth", "hmat_last_error", "hmat_status_string",
             "hmat_batch_create", "hmat_batch_matvec", "hmat_batch_sync", "hmat_batch_set_options",
             "hmat_batch_get_info", "hmat_batch_autotune", "hmat_batch_destroy", "hmat_compress",
-            "hmat_matvec_noalloc")
+            "hmat_matvec_noalloc", "hmat_h2_create", "hmat_h2_matvec", "hmat_h2_destroy", "hmat_h2_get_info",
+            "hmat_h2_set_timing", "hmat_h2_get_timing")
 
 
 class HmatError(RuntimeError):

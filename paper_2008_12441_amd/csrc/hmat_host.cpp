@@ -5,6 +5,8 @@
 #include "hmat_handle.h"
 #include "hmat_compress.h"
 #include "hmat_internal.h"
+#include "hmat_structure.h"
+#include "hmat_host_quant.h"
 
 #include <hip/hip_runtime_api.h>
 
@@ -30,6 +32,16 @@ using hmat::VTile;
 using hmat::ZItem;
 using hmat::ZItem2;
 using hmat::ZSeg;
+using hmat::Tree;
+using hmat::Structure;
+using hmat::analyse_tree;
+using hmat::parallel_for;
+using hmat::validate_blocks;
+using hmat::col_major_amax;
+using hmat::f32_to_bf16_rne;
+using hmat::f32_to_f16_rne;
+using hmat::pow2_scale_f16;
+using hmat::quant16;
 
 namespace {
 
@@ -59,77 +71,6 @@ bool hmat::handle_live(const hmat_handle *h, int add_ref) {
 }
 
 namespace {
-
-template <class F>
-void parallel_for(int64_t n, F f) {
-    unsigned nt = std::thread::hardware_concurrency();
-    nt = std::max(1u, std::min(nt, 16u));
-    if (n < 2 || nt == 1) {
-        for (int64_t i = 0; i < n; ++i) f(i);
-        return;
-    }
-    nt = (unsigned)std::min<int64_t>(nt, n);
-    std::atomic<int64_t> next{0};
-    auto worker = [&]() {
-        for (;;) {
-            int64_t i = next.fetch_add(1);
-            if (i >= n) break;
-            f(i);
-        }
-    };
-    std::vector<std::thread> th;
-    for (unsigned k = 1; k < nt; ++k) th.emplace_back(worker);
-    worker();
-    for (auto &t : th) t.join();
-}
-
-// ---------------------------------------------------------------------------
-// FP16 quantisation (host, bit-defined): power-of-two scale per stored array,
-// s = 2^(ceil(log2 amax) - 15), q = round-to-nearest-even(v / s) in IEEE half.
-// |v / s| <= 2^15 < 65504, and q * s reproduces the stored value exactly.
-// ---------------------------------------------------------------------------
-uint16_t f32_to_f16_rne(float v) {
-    uint32_t x;
-    std::memcpy(&x, &v, 4);
-    const uint32_t sign = (x >> 16) & 0x8000u;
-    const uint32_t ax = x & 0x7fffffffu;
-    if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
-    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to infinity
-    if (ax < 0x38800000u) {                                    // half subnormal range
-        const float f = std::fabs(v) * 16777216.0f;            // exact: units of 2^-24
-        return (uint16_t)(sign | (uint32_t)std::nearbyint(f));
-    }
-    const uint32_t mant = ax & 0x7fffffu;
-    const uint32_t exp = (ax >> 23) - 127 + 15;
-    uint32_t h = (exp << 10) | (mant >> 13);
-    const uint32_t rem = mant & 0x1fffu;
-    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h += 1;
-    return (uint16_t)(sign | h);
-}
-
-// FP32 -> BF16, round to nearest even (NaN stays NaN).
-uint16_t f32_to_bf16_rne(float v) {
-    uint32_t x;
-    std::memcpy(&x, &v, 4);
-    if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
-    const uint32_t lsb = (x >> 16) & 1u;
-    x += 0x7fffu + lsb;
-    return (uint16_t)(x >> 16);
-}
-
-// 16-bit code of v in the storage form: FP16 of v * inv (inv = 1 / scale, a
-// power of two, so the product is exact) or BF16 of v.
-inline uint16_t quant16(float v, float inv, bool bf16) {
-    return bf16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v * inv);
-}
-
-float pow2_scale_f16(float amax) {
-    if (!(amax > 0.0f)) return 1.0f;
-    int e = 0;
-    const float m = std::frexp(amax, &e);  // amax = m 2^e, m in [0.5, 1)
-    const int c = (m == 0.5f) ? e - 1 : e; // ceil(log2 amax)
-    return std::ldexp(1.0f, std::max(c - 15, -126));
-}
 
 // FP8 E4M3 (OCP E4M3FN: bias 7, 3 mantissa bits, subnormals, largest finite
 // 448, no infinities) code of x by round-to-nearest-even; |x| <= 448.
@@ -196,220 +137,6 @@ inline void e4m3_hilo(float v, float sj, float slj, uint8_t *hi, uint8_t *lo) {
     const double u = (double)v / sj;
     *hi = e4m3_rne(u);
     *lo = e4m3_rne((u - e4m3_value(*hi)) / slj);
-}
-
-float col_major_amax(const float *a, int64_t rows, int64_t cols, int64_t ld, bool *finite) {
-    float m = 0.0f;
-    for (int64_t j = 0; j < cols; ++j)
-        for (int64_t i = 0; i < rows; ++i) {
-            const float v = a[i + j * ld];
-            if (!std::isfinite(v)) *finite = false;
-            m = std::max(m, std::fabs(v));
-        }
-    return m;
-}
-
-// ---------------------------------------------------------------------------
-// Tree analysis and structure validation.
-// ---------------------------------------------------------------------------
-struct Tree {
-    int64_t n = 0;
-    int32_t num_nodes = 0;
-    std::vector<int32_t> parent, depth, child_start, child_list, child_pos;
-    std::vector<int64_t> begin, end;
-    int32_t L = 0;
-    int32_t nkids(int32_t p) const { return child_start[p + 1] - child_start[p]; }
-    int32_t kid(int32_t p, int32_t i) const { return child_list[child_start[p] + i]; }
-    bool leaf(int32_t p) const { return nkids(p) == 0; }
-    int64_t size(int32_t p) const { return end[p] - begin[p]; }
-};
-
-hmat_status analyse_tree(const hmat_tree_desc *td, Tree &t) {
-    if (!td) return fail(HMAT_ERR_INVALID_ARG, "tree descriptor is NULL");
-    if (td->n < 1 || td->n >= (int64_t(1) << 31))
-        return fail(HMAT_ERR_INVALID_ARG, "tree n must be in [1, 2^31)");
-    if (td->num_nodes < 1) return fail(HMAT_ERR_INVALID_ARG, "tree needs at least one node");
-    if (td->reserved != 0) return fail(HMAT_ERR_INVALID_ARG, "tree reserved field must be 0");
-    if (!td->parent || !td->begin || !td->end)
-        return fail(HMAT_ERR_INVALID_ARG, "tree arrays must not be NULL");
-    const int32_t nn = td->num_nodes;
-    t.n = td->n;
-    t.num_nodes = nn;
-    t.parent.assign(td->parent, td->parent + nn);
-    t.begin.assign(td->begin, td->begin + nn);
-    t.end.assign(td->end, td->end + nn);
-    if (t.parent[0] != -1) return fail(HMAT_ERR_BAD_TREE, "node 0 must be the root (parent -1)");
-    if (t.begin[0] != 0 || t.end[0] != t.n)
-        return fail(HMAT_ERR_BAD_TREE, "the root must own [0, n)");
-    std::vector<int32_t> count(nn + 1, 0);
-    for (int32_t i = 0; i < nn; ++i) {
-        if (t.begin[i] < 0 || t.end[i] > t.n || t.begin[i] >= t.end[i])
-            return fail(HMAT_ERR_BAD_TREE, "node " + std::to_string(i) + " has an empty or out-of-range index range");
-        if (i > 0) {
-            if (t.parent[i] < 0 || t.parent[i] >= i)
-                return fail(HMAT_ERR_BAD_TREE, "node " + std::to_string(i) + " must have a parent with a smaller id");
-            count[t.parent[i]]++;
-        }
-    }
-    t.child_start.assign(nn + 1, 0);
-    for (int32_t i = 0; i < nn; ++i) t.child_start[i + 1] = t.child_start[i] + count[i];
-    t.child_list.assign(std::max(nn - 1, 0), 0);
-    t.child_pos.assign(nn, 0);
-    std::vector<int32_t> fill(nn, 0);
-    for (int32_t i = 1; i < nn; ++i) {
-        const int32_t p = t.parent[i];
-        t.child_pos[i] = fill[p];
-        t.child_list[t.child_start[p] + fill[p]++] = i;
-    }
-    t.depth.assign(nn, 0);
-    for (int32_t i = 1; i < nn; ++i) t.depth[i] = t.depth[t.parent[i]] + 1;
-    // children (in id order) tile the parent's range contiguously
-    for (int32_t p = 0; p < nn; ++p) {
-        const int32_t k = t.nkids(p);
-        if (k == 0) continue;
-        int64_t cur = t.begin[p];
-        for (int32_t c = 0; c < k; ++c) {
-            const int32_t ch = t.kid(p, c);
-            if (t.begin[ch] != cur)
-                return fail(HMAT_ERR_BAD_TREE, "children of node " + std::to_string(p) + " do not tile its range in id order");
-            cur = t.end[ch];
-        }
-        if (cur != t.end[p])
-            return fail(HMAT_ERR_BAD_TREE, "children of node " + std::to_string(p) + " do not cover its range");
-    }
-    int32_t L = -1;
-    for (int32_t i = 0; i < nn; ++i) {
-        if (!t.leaf(i)) continue;
-        if (L < 0) L = t.depth[i];
-        else if (t.depth[i] != L)
-            return fail(HMAT_ERR_UNSUPPORTED, "leaves at different depths are not supported (the Def. 2.3 "
-                                              "structure then has dense blocks between a leaf and a non-leaf)");
-    }
-    t.L = L;
-    return HMAT_OK;
-}
-
-// The block structure of Def. 2.3: starting from the pair (root, root),
-// every child pair of a recursion pair is a dense block (leaf pairs), a
-// low-rank block (admissible pairs) or a recursion pair itself. The
-// admissibility condition is the caller's: any block set of this shape is
-// accepted, so weak admissibility (low-rank blocks between distinct siblings)
-// and standard admissibility (low-rank blocks between boxes whose parents are
-// neighbours, dense blocks between neighbouring parents' leaves) both are.
-struct Structure {
-    std::unordered_map<uint64_t, int64_t> index;             // (target, source) -> block
-    std::vector<std::vector<int64_t>> by_target, by_source;  // low-rank blocks of a node, by the other node's first row
-    std::vector<std::vector<int32_t>> dense_src;             // per node at depth L-1: the source leaves of its
-                                                             // children's dense blocks, by first row
-    static uint64_t key(int32_t a, int32_t b) { return (uint64_t)(uint32_t)a << 32 | (uint32_t)b; }
-    int64_t find(int32_t a, int32_t b) const {
-        const auto it = index.find(key(a, b));
-        return it == index.end() ? -1 : it->second;
-    }
-};
-
-hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb, Structure &st) {
-    if (!bl) return fail(HMAT_ERR_INVALID_ARG, "blocks pointer is NULL");
-    if (nb < 1) return fail(HMAT_ERR_INVALID_ARG, "num_blocks must be >= 1");
-    const int32_t nn = t.num_nodes;
-    for (int64_t b = 0; b < nb; ++b) {
-        const hmat_block_desc &d = bl[b];
-        const std::string id = "block " + std::to_string(b);
-        if (d.reserved != 0) return fail(HMAT_ERR_INVALID_ARG, id + ": reserved field must be 0");
-        if (d.target < 0 || d.target >= nn || d.source < 0 || d.source >= nn)
-            return fail(HMAT_ERR_INVALID_ARG, id + ": node id out of range");
-        if (d.rank < 0) return fail(HMAT_ERR_INVALID_ARG, id + ": negative rank");
-        if (!d.a) return fail(HMAT_ERR_INVALID_ARG, id + ": factor pointer a is NULL");
-        const int64_t mt = t.size(d.target), ms = t.size(d.source);
-        if (d.lda < mt) return fail(HMAT_ERR_INVALID_ARG, id + ": lda < |t|");
-        if (d.rank > 0) {
-            if (!d.b) return fail(HMAT_ERR_INVALID_ARG, id + ": factor pointer b is NULL");
-            if (d.ldb < ms) return fail(HMAT_ERR_INVALID_ARG, id + ": ldb < |s|");
-            if (d.rank > std::min(mt, ms)) return fail(HMAT_ERR_INVALID_ARG, id + ": rank exceeds min(|t|, |s|)");
-        }
-    }
-    if (t.L == 0) {
-        if (nb != 1 || bl[0].target != 0 || bl[0].source != 0 || bl[0].rank != 0)
-            return fail(HMAT_ERR_BAD_BLOCKS, "a tree whose root is a leaf takes exactly one dense block (0, 0)");
-        return HMAT_OK;
-    }
-    auto name = [&](int64_t b) {
-        return "block " + std::to_string(b) + " (" + std::to_string(bl[b].target) + ", " +
-               std::to_string(bl[b].source) + ")";
-    };
-    st.index.reserve((size_t)nb * 2);
-    for (int64_t b = 0; b < nb; ++b) {
-        const hmat_block_desc &d = bl[b];
-        if (d.target == 0 || d.source == 0)
-            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": the root pair is never a block of Def. 2.3");
-        if (!st.index.emplace(Structure::key(d.target, d.source), b).second)
-            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": duplicate block");
-    }
-    // walk the recursion pairs level by level; every child pair must be a block or recurse
-    std::vector<uint8_t> seen(nb, 0);
-    std::vector<std::vector<int32_t>> partners(nn);
-    std::vector<std::pair<int32_t, int32_t>> frontier{{0, 0}}, next;
-    while (!frontier.empty()) {
-        next.clear();
-        for (const auto &pq : frontier) {
-            const int32_t p = pq.first, q = pq.second;
-            if (t.depth[p] == t.L - 1) partners[p].push_back(q);
-            for (int32_t i = 0; i < t.nkids(p); ++i)
-                for (int32_t j = 0; j < t.nkids(q); ++j) {
-                    const int32_t ct = t.kid(p, i), cs = t.kid(q, j);
-                    const int64_t b = st.find(ct, cs);
-                    const bool leaves = t.leaf(ct);  // all leaves share one depth, and so do ct and cs
-                    if (b < 0) {
-                        if (leaves)
-                            return fail(HMAT_ERR_BAD_BLOCKS, "missing block (" + std::to_string(ct) + ", " +
-                                                                 std::to_string(cs) + ")");
-                        next.emplace_back(ct, cs);
-                        continue;
-                    }
-                    seen[b] = 1;
-                    if (leaves) {
-                        if (bl[b].rank != 0)
-                            return fail(HMAT_ERR_UNSUPPORTED,
-                                        name(b) + ": low-rank blocks between leaves are not supported (Def. 2.3 "
-                                                  "makes them dense)");
-                    } else {
-                        if (ct == cs)
-                            return fail(HMAT_ERR_BAD_BLOCKS,
-                                        name(b) + ": (c, c) above the leaves is a recursion pair, not a block");
-                        if (bl[b].rank == 0)
-                            return fail(HMAT_ERR_UNSUPPORTED,
-                                        name(b) + ": dense blocks between non-leaf boxes are not supported");
-                    }
-                }
-        }
-        frontier.swap(next);
-    }
-    for (int64_t b = 0; b < nb; ++b)
-        if (!seen[b])
-            return fail(HMAT_ERR_BAD_BLOCKS, name(b) + ": not a child pair of a recursion pair (it overlaps "
-                                                       "another block or pairs boxes of different depths)");
-    // low-rank blocks per node, and the dense sources of every depth-(L-1) node
-    st.by_target.assign(nn, {});
-    st.by_source.assign(nn, {});
-    for (int64_t b = 0; b < nb; ++b)
-        if (bl[b].rank > 0) {
-            st.by_target[bl[b].target].push_back(b);
-            st.by_source[bl[b].source].push_back(b);
-        }
-    for (int32_t a = 0; a < nn; ++a) {
-        std::sort(st.by_target[a].begin(), st.by_target[a].end(),
-                  [&](int64_t x, int64_t y) { return t.begin[bl[x].source] < t.begin[bl[y].source]; });
-        std::sort(st.by_source[a].begin(), st.by_source[a].end(),
-                  [&](int64_t x, int64_t y) { return t.begin[bl[x].target] < t.begin[bl[y].target]; });
-    }
-    st.dense_src.assign(nn, {});
-    for (int32_t p = 0; p < nn; ++p) {
-        auto &q = partners[p];
-        std::sort(q.begin(), q.end(), [&](int32_t x, int32_t y) { return t.begin[x] < t.begin[y]; });
-        for (int32_t r : q)
-            for (int32_t j = 0; j < t.nkids(r); ++j) st.dense_src[p].push_back(t.kid(r, j));
-    }
-    return HMAT_OK;
 }
 
 // ---------------------------------------------------------------------------

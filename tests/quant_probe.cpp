@@ -14,6 +14,7 @@
 //                          v / s with the same s); out: s (float32), then one
 //                          16-bit code per value
 #include "../paper_2008_12441_amd/csrc/hmat_host.cpp"
+#include "../paper_2008_12441_amd/csrc/hmat_structure.cpp"
 
 #include <cstdio>
 
@@ -23,6 +24,7 @@ int launch_vphase(const DevPlan &, const float *, void *) { return 1; }
 int launch_zfinish(const DevPlan &, void *) { return 1; }
 int launch_uphase(const DevPlan &, const float *, float *, float, float, void *) { return 1; }
 int launch_probe(const void *, void *, int64_t, int32_t, void *) { return 1; }
+int scratch_address(int, void **) { return 1; }
 int launch_mr(const DevPlanMR &, int32_t, float, const float *, int64_t, float, float *, int64_t, void *,
               void (*)(void *, int), void *) {
     return 1;

@@ -12,11 +12,12 @@ from hmat_inputs import build_tree, make_hmatrix, uniform_tree
 from hmat_testlib import descriptors
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hmat.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^(?:hmat_status|const char \*)\s*(hmat_\w+)\(", text, re.M)))
 
 
