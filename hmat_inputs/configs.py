@@ -106,7 +106,9 @@ def batch_problems(count: int = 256, seed: int = 4, *, nmin: int = 4096, nmax: i
     return out
 
 
-def build_batch_member(spec: dict, *, method: str = "rsvd", seed: int = 0, device=None):
+def build_batch_member(spec: dict, *, method: str = "rsvd", seed: int = 0, device=None,
+                       gpu_min_entries: int = 1 << 24):
+    """Factor set of one member of ``batch_problems`` (see ``make_hmatrix`` for the methods)."""
     tree = build_tree(spec["shape"], n_full=spec["n_full"], offset=spec["offset"])
     return make_hmatrix(tree, spec["rank"], kind=spec["kind"], method=method, seed=seed,
-                        device=device)
+                        device=device, gpu_min_entries=gpu_min_entries)

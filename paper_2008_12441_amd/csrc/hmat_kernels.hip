@@ -48,20 +48,31 @@ __global__ __launch_bounds__(256) void k_uphase(DevPlan p, const float *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Bandwidth probe: grid-stride read (sum kept live) or copy of 16-byte vectors.
+// Bandwidth probe. Read: every wave streams one contiguous span of the buffer
+// (the access pattern of the product kernels, whose waves each walk a panel),
+// 16 nontemporal 16-byte loads per lane in flight, i.e. 16 KiB per wave; the
+// grid is the number of workgroups that fit on the chip at once, so every
+// wave stays resident for the whole read. The sum stays live. Copy: a
+// grid-stride copy of 16-byte vectors.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_probe_read(const f32x4 *__restrict__ src, int64_t n4, float *__restrict__ out) {
+constexpr int kProbeLoads = 16;
+
+__global__ __launch_bounds__(256) void k_probe_read(const f32x4 *__restrict__ src, int64_t n4, int64_t span,
+                                                    float *__restrict__ out) {
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t b0 = wave * span;
+    const int64_t b1 = b0 + span < n4 ? b0 + span : n4;
     f32x4 acc = {0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 7 * stride < n4; i += 8 * stride) {
-        f32x4 v[8];
+    int64_t i = b0;
+    for (; i + kProbeLoads * 64 <= b1; i += kProbeLoads * 64) {
+        f32x4 v[kProbeLoads];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+        for (int u = 0; u < kProbeLoads; ++u) v[u] = __builtin_nontemporal_load(src + i + u * 64 + lane);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
+        for (int u = 0; u < kProbeLoads; ++u) acc += v[u];
     }
-    for (; i < n4; i += stride) acc += src[i];
+    for (i += lane; i < b1; i += 64) acc += src[i];
     __shared__ float red[256];
     red[threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
     __syncthreads();
@@ -165,15 +176,27 @@ int scratch_address(int device, void **ptr) {
 
 int launch_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream) {
     const int64_t n4 = bytes / 16;
-    int64_t blocks = (n4 + 256 * 8 - 1) / (256 * 8);
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    if (mode == 0)
+    if (mode == 0) {
+        // as many workgroups as are resident at once (at most 65536, the size of dst)
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_probe_read, 256, 0);
+        if (e != hipSuccess) return (int)e;
+        int64_t blocks = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+        if (blocks > 65536) blocks = 65536;
+        // each wave's span: whole 16 KiB steps, so only the last wave has a ragged end
+        const int64_t waves = blocks * 4, step = kProbeLoads * 64;
+        const int64_t span = ((n4 + waves - 1) / waves + step - 1) / step * step;
         hipLaunchKernelGGL(k_probe_read, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                           static_cast<const f32x4 *>(src), n4, static_cast<float *>(dst));
-    else
+                           static_cast<const f32x4 *>(src), n4, span, static_cast<float *>(dst));
+    } else {
+        int64_t blocks = (n4 + 256 * 8 - 1) / (256 * 8);
+        if (blocks > 4096) blocks = 4096;
+        if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                            static_cast<const f32x4 *>(src), n4, static_cast<f32x4 *>(dst));
+    }
     return (int)hipGetLastError();
 }
 
