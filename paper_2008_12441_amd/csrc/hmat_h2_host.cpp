@@ -130,19 +130,20 @@ struct H2Host {
     std::vector<int32_t> xh;             // per node: workspace offset of x^ (-1 without a basis)
     int64_t ws_half = 0;
     // small matrices: (destination offset, source, rows, cols, ld, transpose, scale)
-    struct SmallMat {
+    struct SmallMat {          // stored by rows: row r at off + r * sld, entries [0, cols), zeros to sld
         int64_t off;
-        const float *src;
-        int32_t rows, cols;
+        const float *src;          // the given matrix (column-major, ld)
+        int32_t rows, cols;        // of the stored matrix
+        int32_t sld;
         int64_t ld;
-        bool transpose;
+        bool transpose;            // stored = given^T
         float scale;
     };
     std::vector<SmallMat> small;
     int64_t small_elems = 0;
     int64_t v_elems = 0, ud_elems = 0;
     int64_t stored = 0, leaf_kernel_elems = 0;
-    int32_t lds_a = 0, lds_b = 0, kmax = 0;
+    int32_t lds_b = 0, kmax = 0;
 };
 
 hmat_status validate(const Tree &t, const hmat_h2_basis *bases, const hmat_h2_block *blocks, int64_t nb,
@@ -230,11 +231,12 @@ hmat_status build(const Tree &t, const Structure &st, const hmat_h2_basis *bases
         m.src = src;
         m.rows = transpose ? cols : rows;  // rows of the stored matrix
         m.cols = transpose ? rows : cols;
+        m.sld = (m.cols + vw - 1) / vw * vw;
         m.ld = ld;
         m.transpose = transpose;
         m.scale = qz.scale(src, rows, cols, ld, &finite);
         hp.small.push_back(m);
-        hp.small_elems += (int64_t)rows * cols;
+        hp.small_elems += (int64_t)m.rows * m.sld;
         hp.stored += (int64_t)rows * cols;
         return hp.small.size() - 1;
     };
@@ -253,11 +255,11 @@ hmat_status build(const Tree &t, const Structure &st, const hmat_h2_basis *bases
             s_idx[b] = (int64_t)add_small(bl[b].a, rank(bl[b].target), rank(bl[b].source), bl[b].lda, false);
     auto term_of_coupling = [&](int64_t b) {
         const H2Host::SmallMat &m = hp.small[s_idx[b]];
-        return H2Term{(int32_t)m.off, hp.xh[bl[b].source], rank(bl[b].source), 0, m.scale, 0};
+        return H2Term{(int32_t)m.off, hp.xh[bl[b].source], rank(bl[b].source), 0, m.scale, m.sld};
     };
     auto term_of_parent = [&](int32_t a) {
         const H2Host::SmallMat &m = hp.small[e_idx[a]];
-        return H2Term{(int32_t)m.off, hp.xh[t.parent[a]], rank(t.parent[a]), 1, m.scale, 0};
+        return H2Term{(int32_t)m.off, hp.xh[t.parent[a]], rank(t.parent[a]), 1, m.scale, m.sld};
     };
     // nodes above the chunks, by depth
     for (int32_t d = 1; d <= L - 2; ++d)
@@ -270,7 +272,7 @@ hmat_status build(const Tree &t, const Structure &st, const hmat_h2_basis *bases
             for (int32_t j = 0; j < t.nkids(a); ++j) {
                 const int32_t c = t.kid(a, j);
                 const H2Host::SmallMat &m = hp.small[ft_idx[c]];
-                hp.terms.push_back(H2Term{(int32_t)m.off, hp.xh[c], rank(c), 0, m.scale, 0});
+                hp.terms.push_back(H2Term{(int32_t)m.off, hp.xh[c], rank(c), 0, m.scale, m.sld});
             }
             nd.nup = (int32_t)hp.terms.size() - nd.up_base;
             nd.term_base = (int32_t)hp.terms.size();
@@ -308,6 +310,8 @@ hmat_status build(const Tree &t, const Structure &st, const hmat_h2_basis *bases
             e.v_off = hp.v_elems;
             e.ft_off = ft_idx[lf] >= 0 ? (int32_t)hp.small[ft_idx[lf]].off : -1;
             e.e_off = e_idx[lf] >= 0 ? (int32_t)hp.small[e_idx[lf]].off : -1;
+            e.ft_ld = ft_idx[lf] >= 0 ? hp.small[ft_idx[lf]].sld : 0;
+            e.e_ld = e_idx[lf] >= 0 ? hp.small[e_idx[lf]].sld : 0;
             e.sf = ft_idx[lf] >= 0 ? hp.small[ft_idx[lf]].scale : 1.0f;
             e.se = e_idx[lf] >= 0 ? hp.small[e_idx[lf]].scale : 1.0f;
             e.sv = e.k > 0 ? qz.scale(bases[lf].v, e.rows, e.k, bases[lf].ldv, &finite) : 1.0f;
@@ -352,13 +356,12 @@ hmat_status build(const Tree &t, const Structure &st, const hmat_h2_basis *bases
             }
         m.ud_off = hp.ud_elems;
         hp.ud_elems += (int64_t)((m.rows + hmat::kWave - 1) / hmat::kWave) * nq * hmat::kWave * vw;
-        hp.lds_a = std::max(hp.lds_a, m.nleaf * 64 + 256);
         hp.lds_b = std::max(hp.lds_b, 320 + m.nleaf * m.nq_u * vw + vec);
         hp.chunks.push_back(m);
     }
     if (!finite) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
-    if (hp.lds_a > kMaxLdsFloats || hp.lds_b > kMaxLdsFloats)
-        return fail(HMAT_ERR_UNSUPPORTED, "a chunk's leaf-kernel operands (" + std::to_string(std::max(hp.lds_a, hp.lds_b)) +
+    if (hp.lds_b > kMaxLdsFloats)
+        return fail(HMAT_ERR_UNSUPPORTED, "a chunk's leaf-kernel operands (" + std::to_string(hp.lds_b) +
                                               " floats) exceed the LDS budget of " + std::to_string(kMaxLdsFloats));
     if (hp.small_elems >= INT32_MAX || hp.terms.size() >= (size_t)INT32_MAX)
         return fail(HMAT_ERR_UNSUPPORTED, "too many transfer and coupling entries");
@@ -431,10 +434,11 @@ void fill(const Tree &t, const Structure &st, const hmat_h2_basis *bases, const 
     // small matrices
     hmat::parallel_for((int64_t)hp.small.size(), [&](int64_t k) {
         const H2Host::SmallMat &m = hp.small[k];
-        for (int32_t j = 0; j < m.cols; ++j)
-            for (int32_t i = 0; i < m.rows; ++i) {
-                const float x = m.transpose ? m.src[j + (int64_t)i * m.ld] : m.src[i + (int64_t)j * m.ld];
-                small[m.off + i + (int64_t)j * m.rows] = code(x, m.scale);
+        for (int32_t r = 0; r < m.rows; ++r)
+            for (int32_t c = 0; c < m.sld; ++c) {
+                float x = 0.0f;
+                if (c < m.cols) x = m.transpose ? m.src[c + (int64_t)r * m.ld] : m.src[r + (int64_t)c * m.ld];
+                small[m.off + (int64_t)r * m.sld + c] = code(x, m.scale);
             }
     });
 }
@@ -481,7 +485,6 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_h2_basis *bases, 
     p.L = t.L;
     p.num_chunks = (int32_t)hp.chunks.size();
     p.kmax = hp.kmax;
-    p.lds_a_floats = hp.lds_a;
     p.lds_b_floats = hp.lds_b;
     p.ws_half = (int32_t)hp.ws_half;
     // levels above the chunks: the node list holds depth 1, then depth 2, ... up to L-2
@@ -619,7 +622,7 @@ hmat_status hmat_h2_matvec(hmat_h2_t h, int32_t nrhs, float alpha, const float *
         int e = 0;
         if (h->timing && (s = record_event(h, st)) != HMAT_OK) return s;
         if (L >= 2) {
-            if ((e = hmat::launch_h2_upleaf(p, xc, st)) != 0) return dev_fail("upward leaf launch", e);
+            if ((e = hmat::launch_h2_upward(p, xc, st)) != 0) return dev_fail("upward launch", e);
             for (int32_t d = L - 2; d >= 1; --d)
                 if ((e = hmat::launch_h2_up(p, h->level_first[d], h->level_count[d], st)) != 0)
                     return dev_fail("upward level launch", e);

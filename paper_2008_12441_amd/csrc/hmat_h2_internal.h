@@ -18,10 +18,11 @@
 //    then the dense leaf blocks grouped by source leaf (each padded to VW
 //    columns), the same form as the H-matrix's target-side panel.
 //
-//  * Small matrices (transfers and couplings) in one array, column-major:
-//    E_t (k_t x k_parent) as given, F_t stored transposed (k_parent x k_t) so
-//    that the upward pass reads it with lane = output index, couplings S_ts
-//    (k_t x k_s) as given.
+//  * Small matrices (transfers and couplings) in one array, stored by rows
+//    (each row padded to a multiple of 16 bytes, every matrix 16-byte aligned),
+//    so that a lane owning one output reads its row in 16-byte loads: E_t
+//    (k_t x k_parent), F_t transposed (k_parent x k_t), couplings S_ts
+//    (k_t x k_s).
 //
 //  * Workspace: x^ and y^ of every node with a basis (k_t values each).
 #pragma once
@@ -40,6 +41,8 @@ struct H2Leaf {
     int64_t v_off;        // element offset of its V tiles in the V panel
     int32_t ft_off;       // F^T of the leaf (k_chunk x k) in the small array, -1 when the chunk has no basis
     int32_t e_off;        // E of the leaf (k x k_chunk), -1 likewise
+    int32_t ft_ld;        // their row strides in the small array
+    int32_t e_ld;
     float sv;             // scales of its stored V, U, F and E arrays (1 in FP32)
     float su;
     float sf;
@@ -68,12 +71,12 @@ struct H2Chunk {
 // M = E_t and w = y^_parent, or M = S_ts and w = x^_s) or x^ (upward pass:
 // x^_t += s * M w with M = F_c^T and w = x^_c).
 struct H2Term {
-    int32_t m_off;        // small-array offset of M (k_t rows, column-major)
+    int32_t m_off;        // small-array offset of M (k_t rows, stored by rows)
     int32_t src;          // workspace offset of w: x^ entries, or y^ entries (y_from = 1)
     int32_t cols;         // length of w
     int32_t y_from;       // w comes from the y^ half of the workspace
     float scale;
-    int32_t pad_;
+    int32_t ldm;          // row stride of M
 };
 
 struct H2Node {           // a node above the chunks (depth 1 .. L-2)
@@ -90,10 +93,8 @@ struct DevPlanH2 {
     int32_t L;
     int32_t num_chunks;
     int32_t kmax;             // largest basis rank
-    int32_t lds_a_floats;     // dynamic LDS of the upward leaf kernel
     int32_t lds_b_floats;     // dynamic LDS of the leaf kernel
     int32_t ws_half;          // floats in each half (x^, y^) of the workspace
-    int32_t pad_;
     const void *V;
     const void *UD;
     const void *small;        // transfers and couplings (float or _Float16 codes)
@@ -107,7 +108,7 @@ struct DevPlanH2 {
 };
 
 // Launchers (hmat_h2.hip); each returns a hipError_t as int.
-int launch_h2_upleaf(const DevPlanH2 &p, const float *x, void *stream);
+int launch_h2_upward(const DevPlanH2 &p, const float *x, void *stream);
 int launch_h2_up(const DevPlanH2 &p, int32_t first, int32_t count, void *stream);
 int launch_h2_down(const DevPlanH2 &p, int32_t first, int32_t count, void *stream);
 int launch_h2_leaf(const DevPlanH2 &p, const float *x, float *y, float alpha, float beta, void *stream);
