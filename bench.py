@@ -119,12 +119,15 @@ def probe_bandwidth(stream, nbytes=4 << 30, reps=5):
 SV_SOURCES = ("hmat_kernels.hip", "hmat_sv_device.h", "hmat_device_common.h", "hmat_internal.h")
 
 
-def kernel_source_digest():
-    """First 16 hex digits of the sha256 over the sources of the single-vector kernels."""
+MR_SOURCES = ("hmat_mr_kernels.hip", "hmat_mr_device.h", "hmat_device_common.h", "hmat_internal.h")
+
+
+def kernel_source_digest(sources=SV_SOURCES):
+    """First 16 hex digits of the sha256 over the sources of a set of kernels."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in SV_SOURCES:
+    for name in sources:
         h.update(open(os.path.join(ROOT, "paper_2008_12441_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -162,6 +165,18 @@ def host_cpu():
         pass
     return {"model": model, "sockets": len(sockets) or None, "logical_cpus": logical or None,
             "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def mr_counters(workload):
+    """HBM traffic and MFMA utilisation of the multi-RHS group kernels from the committed
+    counter summary, or None once their sources changed after the counters were taken."""
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "mr_c3_c5_counters.json")))
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_source_sha256_16") != kernel_source_digest(MR_SOURCES):
+        return None
+    return prof.get(workload)
 
 
 def time_fn(fn, steps, warmup, stream):
@@ -366,6 +381,7 @@ def run_large_3d(stream, steps, warmup, with_oracle=True, forms=("fp32", "fp16",
     if "fp32" in out:
         out["roofline_fp32"] = {"bound": "mfma", "peak": 157.3, "unit": "TFLOP/s",
                                 "frac": round(out["fp32"]["TFLOPps"] / 157.3, 4)}
+    out["counters"] = mr_counters("c5")
     if "fp8" in out:
         out["roofline_fp8"] = {"bound": "hbm", "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                "frac": round(out["fp8"]["GBps"] / HBM_PEAK_GBPS, 4)}
@@ -427,6 +443,7 @@ def run_multi_rhs(stream, steps, warmup, with_oracle=True, method=None, forms=("
             out[f"{form}_speedup_vs_fp32"] = round(out["fp32"]["ms_per_step"] / out[form]["ms_per_step"], 3)
             out["roofline"][form] = {"bound": "hbm", "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                      "frac": round(out[form]["GBps"] / HBM_PEAK_GBPS, 4)}
+    out["counters"] = mr_counters("c3")
     if with_oracle:
         import oracle
         from oracle.quant import dequantised
