@@ -593,6 +593,19 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             for (int32_t ls : src) hp.dscale.push_back(hp.sD[L == 0 ? 0 : st.find(lt, ls)]);
         hp.chunks.push_back(m);
     }
+    // Source side: the chunk's rows need no leaf alignment there, so its X
+    // fragments are also kept with the rows contiguous and padded once, at the
+    // chunk's end. The two coincide when every leaf but the last is a whole
+    // number of K-blocks; otherwise every chunk gets the contiguous copy, after
+    // all the per-leaf ones, so that a unit's chunks stay consecutive.
+    bool aligned = true;
+    for (const hmat::MRChunk &m : hp.chunks)
+        for (int32_t lf = 0; lf + 1 < m.nleaf; ++lf) aligned = aligned && hp.leaves[m.leaf_base + lf].rows % KB == 0;
+    for (hmat::MRChunk &m : hp.chunks) {
+        m.nkbv = (m.rows + KB - 1) / KB;
+        m.xvoff = aligned ? m.xoff : xf;
+        if (!aligned) xf += (int64_t)m.nkbv * hp.ntmax;
+    }
     hp.x_frags = xf;
     // V units: per level-l source box s and 64-column group, at most kUnitChunks chunks each
     hp.colmap.assign(t.num_nodes, {});
@@ -632,7 +645,7 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                     u.nc = std::min(kUnitChunks, c1 - u.c0);
                     u.nm = nm;
                     u.poff = (int64_t)hp.vunits.size() * 64 * hp.ntmax * 16;
-                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) af += (int64_t)hp.chunks[c].nkb * nm;
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) af += (int64_t)hp.chunks[c].nkbv * nm;
                     hp.vunits.push_back(u);
                     hp.unit_node.push_back(s);
                     hp.unit_group.push_back(g);
@@ -783,16 +796,6 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
     return HMAT_OK;
 }
 
-// Position of padded row pr of chunk c: global row, or -1 for padding.
-inline int32_t mr_row(const HostPlanMR &hp, const hmat::MRChunk &m, int32_t pr) {
-    const int32_t kb = pr / hp.kb;
-    int32_t lf = 0;
-    while (lf + 1 < m.nleaf && hp.leaves[m.leaf_base + lf + 1].kb0 <= kb) ++lf;
-    const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
-    const int32_t o = pr - e.kb0 * hp.kb;
-    return o < e.rows ? e.row_begin + o : -1;
-}
-
 template <class T>
 inline T quant(float v, float scale, bool bf16) {
     if constexpr (sizeof(T) == 4) {
@@ -814,15 +817,15 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
         int64_t af = u.aoff;
         for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) {
             const hmat::MRChunk &m = hp.chunks[c];
-            for (int32_t kb = 0; kb < m.nkb; ++kb)
+            for (int32_t kb = 0; kb < m.nkbv; ++kb)
                 for (int32_t ms = 0; ms < u.nm; ++ms) {
                     T *fr = out + (af + (int64_t)kb * u.nm + ms) * 64 * vw;
                     for (int32_t l = 0; l < 64; ++l) {
                         const int32_t col = 64 * g + 16 * ms + l % 16;
                         uint8_t hi[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int32_t e = 0; e < vw; ++e) {
-                            const int32_t pr = kb * KB + vw * (l / 16) + e;
-                            const int32_t gr = mr_row(hp, m, pr);
+                            const int32_t pr = kb * KB + vw * (l / 16) + e;  // the chunk's rows, contiguous
+                            const int32_t gr = pr < m.rows ? m.row_begin + pr : -1;
                             float v = 0.0f, sc = 1.0f;
                             if (gr >= 0 && col < (int32_t)cm.size()) {
                                 const int64_t b = cm[col].first;
@@ -843,7 +846,7 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
                             }
                     }
                 }
-            af += (int64_t)m.nkb * u.nm;
+            af += (int64_t)m.nkbv * u.nm;
         }
     });
 }
@@ -1139,7 +1142,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 int64_t bytes = 0;
                 for (int32_t i = g.u0; i < g.u0 + g.count; ++i) {
                     const hmat::MRVUnit &u = hpm.vunits[i];
-                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkb * u.nm * 1024;
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkbv * u.nm * 1024;
                 }
                 h->cost_src.push_back((float)bytes);
             }

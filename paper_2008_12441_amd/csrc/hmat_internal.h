@@ -127,13 +127,19 @@ struct DevPlan {
 //    A B fragment is KB inner indices x 16 columns with the mirrored lane
 //    mapping (lane l: column l % 16, inner indices VW * (l / 16) + [0, VW)),
 //    1 KiB for FP32, 2 KiB for FP16 (a high and a low half-precision part).
-//  * Rows of every chunk are padded leaf by leaf to multiples of KB, so each
-//    leaf starts on a K-block boundary.
-//  * V panel: per unit (level, source box, 64-column group, up to 16 chunks of
-//    that box) the A fragments [chunk][K-block][m-subtile]; a wave computes
-//    the unit's V^T X and writes its partial sums (64 x 16 NT floats).
-//  * Xpack: per chunk the B fragments [K-block][n-tile] of X (FP16: hi/lo
-//    with one power-of-two scale per chunk and n-tile of 16 columns).
+//  * Target side: rows of every chunk are padded leaf by leaf to multiples of
+//    KB, so each leaf starts on a K-block boundary (a dense block's columns
+//    are one source leaf). Source side: a chunk's rows are taken contiguously
+//    and padded once, at the chunk's end (the same thing when every leaf but
+//    the last is a whole number of K-blocks).
+//  * V panel: per unit (level, source box, 64-column group, up to 4 chunks of
+//    that box) the A fragments [chunk][K-block of its contiguous rows]
+//    [m-subtile]; a wave computes the unit's V^T X and writes its partial sums
+//    (64 x 16 NT floats).
+//  * Xpack: per chunk the B fragments [K-block][n-tile] of X in the leaf-padded
+//    row order, then (unless the two coincide) per chunk those of the
+//    contiguous row order; FP16: hi/lo with one power-of-two scale per chunk
+//    and n-tile of 16 columns, shared by both copies.
 //  * Zpack: per low-rank block the B fragments [K-block][n-tile] of its z
 //    (FP16: hi/lo, one power-of-two scale per block and n-tile).
 //  * UD panel: per row tile (<= 64 rows of one target leaf) the A fragments
@@ -143,7 +149,7 @@ struct DevPlan {
 struct MRChunk {
     int32_t row_begin;
     int32_t rows;
-    int32_t nkb;          // K-blocks of its leaf-padded rows
+    int32_t nkb;          // K-blocks of its leaf-padded rows (the target-side x segments)
     int32_t leaf_base;    // first entry in the leaf table
     int32_t nleaf;        // its leaves (the target leaves of its rows)
     int32_t seg_base;     // first U-phase segment
@@ -155,7 +161,8 @@ struct MRChunk {
     int32_t ulo_base;     // FP8 forms: first of its 32 x nzsteps U lo-scales in ulo
     int32_t nzsteps;      // steps over z segments (they come first)
     int32_t nsrc;         // source leaves of its dense blocks
-    int32_t pad_;
+    int32_t nkbv;         // K-blocks of its rows taken contiguously (the source-side contraction)
+    int64_t xvoff;        // first B fragment of those (relative to xpack): xoff when the two coincide
 };
 
 struct MRLeaf {

@@ -427,7 +427,8 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
 // 16 nt + l % 16, which is where they sit in the fragment. The first four
 // K-blocks of every wave stay in registers between the amax and the split, so
 // a chunk of up to 16 K-blocks (512 rows in FP16) reads X once; the rest of a
-// longer chunk is read a second time.
+// longer chunk is read a second time. Where the chunk's leaves are not whole
+// K-blocks, the source side's copy (rows contiguous) is written as well.
 // ---------------------------------------------------------------------------
 template <int STORE>
 __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx, int k,
@@ -500,6 +501,17 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
         gather(kb, t);
         store(kb, t, inv);
     }
+    if (ch.xvoff != ch.xoff)  // the source side's copy: the chunk's rows contiguous
+        for (int kb = wave; kb < ch.nkbv; kb += 4) {
+            const int off0 = kb * KB + VW * (lane >> 4);
+            float t[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const int o = off0 + e;
+                t[e] = (n < k && o < ch.rows) ? col[ch.row_begin + o] * inv : 0.0f;
+            }
+            F::storeB(p.xpack, ch.xvoff + (int64_t)kb * p.ntmax + nt, lane, t);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -563,6 +575,15 @@ __device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const fl
         for (int e = 0; e < VW; ++e) t[e] = off0 + e < L.rows ? src[off0 + e] * inv : 0.0f;
         F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, t);
     }
+    if (ch.xvoff != ch.xoff)  // the source side's copy: the chunk's rows contiguous
+        for (int kb = wave; kb < ch.nkbv; kb += 4) {
+            const int off0 = kb * KB + VW * (lane >> 4);
+            const float *src = tile + j * rs;
+            float t[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) t[e] = off0 + e < ch.rows ? src[off0 + e] * inv : 0.0f;
+            F::storeB(p.xpack, ch.xvoff + (int64_t)kb * p.ntmax + nt, lane, t);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -991,10 +1012,10 @@ __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *
 #pragma unroll
     for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
     int nsteps = 0;
-    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
+    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkbv;
     int vn = 0;  // lane j: K-blocks of the unit's chunk j
     if (lane < u.nc) {
-        vn = p.chunks[u.c0 + lane].nkb;
+        vn = p.chunks[u.c0 + lane].nkbv;
         if (F::SCALED)
 #pragma unroll
             for (int t = 0; t < NT; ++t) sv[t] = p.sx[(int64_t)(u.c0 + lane) * p.ntmax + t];
@@ -1020,7 +1041,7 @@ __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *
             return a;
         }
     };
-    const int64_t b0 = cload(p.chunks, u.c0).xoff, ntm = p.ntmax;
+    const int64_t b0 = cload(p.chunks, u.c0).xvoff, ntm = p.ntmax;
     constexpr int64_t bbytes = 16 * F::BFRAG;
     auto bofs_of = [&](int st) -> int64_t { return (b0 + (int64_t)st * ntm) * bbytes; };
     int c = 0, cend = 0;  // chunk (index in the unit) of the step asked for last, and the step where it ends
