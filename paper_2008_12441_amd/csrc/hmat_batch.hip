@@ -89,6 +89,7 @@ __device__ inline DevPlanMR load_plan_mr(const DevPlanMR *m) {
     HMAT_GLOBAL_FIELD(p, m, leaves);
     HMAT_GLOBAL_FIELD(p, m, vunits);
     HMAT_GLOBAL_FIELD(p, m, zitems);
+    HMAT_GLOBAL_FIELD(p, m, zmembers);
     HMAT_GLOBAL_FIELD(p, m, segs);
     HMAT_GLOBAL_FIELD(p, m, tiles);
     HMAT_GLOBAL_FIELD(p, m, ustep);

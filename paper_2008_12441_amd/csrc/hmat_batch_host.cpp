@@ -294,7 +294,7 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
             if (h->max_nseg > 64)
                 return set_error(HMAT_ERR_UNSUPPORTED, "member " + std::to_string(i) + ": more than 64 target-side segments per chunk");
             b->has_m = true;
-            b->zs_rank = std::max(b->zs_rank, h->max_rank);
+            b->zs_rank = std::max(b->zs_rank, h->max_zrows);
             const int32_t rows = h->mrp.max_chunk_rows;
             if (rows <= 512)  // X packing through an LDS tile: 16 columns of a chunk, then four maxima
                 b->lds = std::max(b->lds, (size_t)(16 * (rows + 1) + 4) * 4);

@@ -28,6 +28,7 @@ struct hmat_handle {
     std::vector<int32_t> chunk_rows;  // rows of each chunk
     int32_t max_nseg = 0;             // multi-RHS: most target-side segments of a chunk
     int32_t max_rank = 0;             // largest rank of a low-rank block
+    int32_t max_zrows = 0;            // multi-RHS: most z rows of a z item (the blocks of one target box)
     // single-vector workspace sizes in bytes (partial sums; z vectors; stage-1 slices)
     int64_t ws_part_bytes = 0, ws_zg_bytes = 0, ws_slice_bytes = 0;
     int32_t batch_refs = 0;           // batches that reference this handle (guarded by the registry lock)

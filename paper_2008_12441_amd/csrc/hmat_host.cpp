@@ -484,9 +484,10 @@ struct HostPlanMR {
     std::vector<hmat::MRVUnit> vunits;
     std::vector<int32_t> unit_node, unit_group;
     std::vector<hmat::MRZItem> zitems;
-    std::vector<int64_t> zitem_block;
+    std::vector<hmat::MRZMember> zmembers;
+    std::vector<int64_t> zmember_block;        // low-rank block of each z item member
+    std::vector<std::vector<int32_t>> zrow_member;  // per z item: the member holding each row
     std::vector<hmat::MRSeg> segs;
-    std::vector<int64_t> seg_block;            // low-rank block of a z segment, or -1
     std::vector<int32_t> seg_node;             // source leaf node of an x segment
     std::vector<hmat::MRTile> tiles;
     std::vector<hmat::MRTileGroup> tgroups;
@@ -686,29 +687,60 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         hp.ugroups.push_back(hmat::MRUnitGroup{i, j - i});
         i = j;
     }
-    // z items: one per low-rank block
-    std::vector<int32_t> zitem_of(nb, -1);
+    // z items: a block whose rank is a whole number of K-blocks is an item of its
+    // own; the others of one target box, in its block order, are stacked into
+    // shared K-blocks (a box whose stacked ranks add up to more than kMaxRankMR
+    // continues in a further item)
+    std::vector<int32_t> zfirst(t.num_nodes, 0), zcount(t.num_nodes, 0);
     int64_t zf = 0;
-    for (int64_t b = 0; b < nb && L >= 2; ++b) {
-        if (bl[b].rank == 0) continue;
-        const int32_t s = bl[b].source;
+    for (int32_t a = 0; a < t.num_nodes && L >= 2; ++a) {
+        if (st.by_target[a].empty()) continue;
+        zfirst[a] = (int32_t)hp.zitems.size();
         hmat::MRZItem z{};
-        z.ubase = ubase[s];
-        z.nu = nunit[s];
-        z.vcol = vcol[b];
-        z.rank = bl[b].rank;
-        z.scale = hp.sU[b] * hp.sV[b];
-        z.col_off = 0;
-        if (hp.fp8) {
-            z.scale = 1.0f;
-            z.col_off = (int32_t)hp.zcol.size();
-            for (int32_t j = 0; j < bl[b].rank; ++j) hp.zcol.push_back(hp.colU[b][2 * j] * hp.colV[b][2 * j]);
+        auto finish = [&]() {
+            z.zoff = zf;
+            zf += (int64_t)((z.rows + KB - 1) / KB) * hp.ntmax;
+            std::vector<int32_t> rm(z.rows);
+            for (int32_t i = z.m0; i < z.m0 + z.nmem; ++i)
+                for (int32_t j = 0; j < hp.zmembers[i].rank; ++j) rm[hp.zmembers[i].row + j] = i;
+            hp.zrow_member.push_back(std::move(rm));
+            hp.zitems.push_back(z);
+        };
+        z.m0 = (int32_t)hp.zmembers.size();
+        std::vector<int64_t> order;  // the stacked blocks, then the whole-K-block ones
+        for (const int64_t b : st.by_target[a])
+            if (bl[b].rank % KB != 0) order.push_back(b);
+        const size_t nstack = order.size();
+        for (const int64_t b : st.by_target[a])
+            if (bl[b].rank % KB == 0) order.push_back(b);
+        for (size_t i = 0; i < order.size(); ++i) {
+            const int64_t b = order[i];
+            if (z.nmem > 0 && (i >= nstack || z.rows + bl[b].rank > kMaxRankMR)) {
+                finish();
+                z = hmat::MRZItem{};
+                z.m0 = (int32_t)hp.zmembers.size();
+            }
+            const int32_t s = bl[b].source;
+            hmat::MRZMember zm{};
+            zm.ubase = ubase[s];
+            zm.nu = nunit[s];
+            zm.vcol = vcol[b];
+            zm.rank = bl[b].rank;
+            zm.scale = hp.sU[b] * hp.sV[b];
+            zm.col_off = 0;
+            zm.row = z.rows;
+            if (hp.fp8) {
+                zm.scale = 1.0f;
+                zm.col_off = (int32_t)hp.zcol.size();
+                for (int32_t j = 0; j < bl[b].rank; ++j) hp.zcol.push_back(hp.colU[b][2 * j] * hp.colV[b][2 * j]);
+            }
+            hp.zmembers.push_back(zm);
+            hp.zmember_block.push_back(b);
+            ++z.nmem;
+            z.rows += bl[b].rank;
         }
-        z.zoff = zf;
-        zf += (int64_t)((bl[b].rank + KB - 1) / KB) * hp.ntmax;
-        zitem_of[b] = (int32_t)hp.zitems.size();
-        hp.zitems.push_back(z);
-        hp.zitem_block.push_back(b);
+        if (z.nmem > 0) finish();
+        zcount[a] = (int32_t)hp.zitems.size() - zfirst[a];
     }
     hp.z_frags = zf;
     // U-phase segments per chunk, and row tiles per target leaf
@@ -719,12 +751,11 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         int32_t seg_kb = 0;
         for (int32_t lvl = 1; lvl <= L - 1; ++lvl) {
             const int32_t a = hp.anc[(size_t)c * (cd + 1) + lvl];
-            for (const int64_t b : st.by_target[a]) {
-                const hmat::MRZItem &z = hp.zitems[zitem_of[b]];
-                hmat::MRSeg sg{z.zoff, (bl[b].rank + KB - 1) / KB, 0, zitem_of[b], 0};
+            for (int32_t zi = zfirst[a]; zi < zfirst[a] + zcount[a]; ++zi) {
+                const hmat::MRZItem &z = hp.zitems[zi];
+                hmat::MRSeg sg{z.zoff, (z.rows + KB - 1) / KB, 0, zi, 0};
                 seg_kb += sg.nkb;
                 hp.segs.push_back(sg);
-                hp.seg_block.push_back(b);
                 hp.seg_node.push_back(-1);
             }
         }
@@ -737,7 +768,6 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             hmat::MRSeg sg{ms.xoff + (int64_t)e.kb0 * hp.ntmax, e.nkb, 1, sc, is};
             seg_kb += sg.nkb;
             hp.segs.push_back(sg);
-            hp.seg_block.push_back(-1);
             hp.seg_node.push_back(src[is]);
         }
         m.nseg = (int32_t)hp.segs.size() - m.seg_base;
@@ -750,9 +780,15 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             if (sg.kind != 0) continue;
             m.nzsteps += sg.nkb;
             if (!hp.fp8) continue;
-            const int64_t b = hp.seg_block[si];
-            for (int32_t k = 0; k < sg.nkb * KB; ++k)  // lo-scales of the block's U columns, K-block by K-block
-                hp.ulo.push_back(f16_pow2_code(k < bl[b].rank ? hp.colU[b][2 * k + 1] : 1.0));
+            const hmat::MRZItem &z = hp.zitems[sg.sidx];
+            for (int32_t k = 0; k < sg.nkb * KB; ++k) {  // lo-scales of the item's U columns, K-block by K-block
+                if (k >= z.rows) {
+                    hp.ulo.push_back(f16_pow2_code(1.0));
+                    continue;
+                }
+                const int32_t mi = hp.zrow_member[sg.sidx][k];
+                hp.ulo.push_back(f16_pow2_code(hp.colU[hp.zmember_block[mi]][2 * (k - hp.zmembers[mi].row) + 1]));
+            }
         }
         const int64_t bbytes = KB == 32 ? 2048 : 1024;
         for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
@@ -861,14 +897,18 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
         int64_t af = tl.aoff;
         for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
             const hmat::MRSeg &sg = hp.segs[si];
-            const int64_t lb = hp.seg_block[si];
+            const bool zseg = sg.kind == 0;
+            // z segment: column kk is column kk - row of the member block holding
+            // row kk of the z item; x segment: column kk of the dense block
             int64_t db = -1;
-            if (sg.kind == 1) db = (t.L == 0) ? 0 : st.find(tnode, hp.seg_node[si]);
-            const hmat_block_desc &d = bl[sg.kind == 0 ? lb : db];
-            const int32_t ncols = sg.kind == 0 ? d.rank : (int32_t)t.size(hp.seg_node[si]);
-            const int32_t rbase = (int32_t)(sg.kind == 0 ? t.begin[d.target] : t.begin[tnode]);
-            const float sc = sg.kind == 0 ? hp.sU[lb] : hp.sD[db];
-            const bool hilo = hp.fp8 && sg.kind == 0;
+            int32_t ncols = 0;
+            if (zseg) {
+                ncols = hp.zitems[sg.sidx].rows;
+            } else {
+                db = (t.L == 0) ? 0 : st.find(tnode, hp.seg_node[si]);
+                ncols = (int32_t)t.size(hp.seg_node[si]);
+            }
+            const bool hilo = hp.fp8 && zseg;
             for (int32_t kb = 0; kb < sg.nkb; ++kb)
                 for (int32_t ms = 0; ms < tl.nm; ++ms) {
                     T *fr = out + (af + (int64_t)kb * tl.nm + ms) * 64 * vw;
@@ -877,12 +917,23 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
                         uint8_t hi[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int32_t e = 0; e < vw; ++e) {
                             const int32_t kk = kb * KB + vw * (l / 16) + e;
+                            int64_t b = db;
+                            int32_t col = kk;
+                            if (zseg && kk < ncols) {
+                                const int32_t mi = hp.zrow_member[sg.sidx][kk];
+                                b = hp.zmember_block[mi];
+                                col = kk - hp.zmembers[mi].row;
+                            }
+                            const float sc = kk >= ncols ? 1.0f : zseg ? hp.sU[b] : hp.sD[db];
                             float v = 0.0f;
-                            if (tr < tl.rows && kk < ncols)
-                                v = d.a[(tl.row0 + tr - rbase) + (int64_t)kk * d.lda];
+                            if (tr < tl.rows && kk < ncols) {
+                                const hmat_block_desc &d = bl[b];
+                                const int32_t rbase = (int32_t)(zseg ? t.begin[d.target] : t.begin[tnode]);
+                                v = d.a[(tl.row0 + tr - rbase) + (int64_t)col * d.lda];
+                            }
                             if (hilo) {
-                                if (kk < ncols) e4m3_hilo(v, hp.colU[lb][2 * kk], hp.colU[lb][2 * kk + 1], &hi[e], &lo[e]);
-                            } else if (hp.dense_bf16 && sg.kind == 1) {
+                                if (kk < ncols) e4m3_hilo(v, hp.colU[b][2 * col], hp.colU[b][2 * col + 1], &hi[e], &lo[e]);
+                            } else if (hp.dense_bf16 && !zseg) {
                                 fr[l * vw + e] = (T)f32_to_bf16_rne(v * (1.0f / sc));  // BF16 of v / s_D
                             } else {
                                 fr[l * vw + e] = quant<T>(v, sc, hp.bf16);
@@ -994,6 +1045,7 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     if ((s = upload(h, hp.leaves, &p.leaves)) != HMAT_OK) return s;
     if ((s = upload(h, hp.vunits, &p.vunits)) != HMAT_OK) return s;
     if ((s = upload(h, hp.zitems, &p.zitems)) != HMAT_OK) return s;
+    if ((s = upload(h, hp.zmembers, &p.zmembers)) != HMAT_OK) return s;
     if ((s = upload(h, hp.segs, &p.segs)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tiles, &p.tiles)) != HMAT_OK) return s;
     if ((s = upload(h, hp.tgroups, &p.tgroups)) != HMAT_OK) return s;
@@ -1132,6 +1184,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
         constexpr float kLatencyBytes = 4096.0f;
         const float esz = opts->storage == HMAT_STORE_FP32 ? 4.0f : 2.0f;
         if (h->mr) {
+            for (const hmat::MRZItem &z : hpm.zitems) h->max_zrows = std::max(h->max_zrows, z.rows);
             for (const hmat::MRChunk &c : hpm.chunks) {
                 h->chunk_rows.push_back(c.rows);
                 h->max_nseg = std::max(h->max_nseg, c.nseg);
@@ -1154,8 +1207,11 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
             }
             // partials read and B fragments written (one n-tile), plus a latency term: these small
             // items are bound by round trips, not bytes
-            for (const hmat::MRZItem &z : hpm.zitems)
-                h->cost_z1.push_back((float)z.nu * z.rank * 64 + (float)z.rank * 64 * 2 + kLatencyBytes);
+            for (const hmat::MRZItem &z : hpm.zitems) {
+                float c = (float)z.rows * 64 * 2 + kLatencyBytes;
+                for (int32_t i = z.m0; i < z.m0 + z.nmem; ++i) c += (float)hpm.zmembers[i].nu * hpm.zmembers[i].rank * 64;
+                h->cost_z1.push_back(c);
+            }
         } else {
             for (const ChunkMeta &c : hp.chunks) {
                 h->chunk_rows.push_back(c.rows);

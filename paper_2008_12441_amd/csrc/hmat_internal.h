@@ -140,11 +140,14 @@ struct DevPlan {
 //    row order, then (unless the two coincide) per chunk those of the
 //    contiguous row order; FP16: hi/lo with one power-of-two scale per chunk
 //    and n-tile of 16 columns, shared by both copies.
-//  * Zpack: per low-rank block the B fragments [K-block][n-tile] of its z
-//    (FP16: hi/lo, one power-of-two scale per block and n-tile).
+//  * Zpack: per z item (the low-rank blocks of one target box, up to 128 rows
+//    of z in all) the B fragments [K-block][n-tile] of their z stacked in the
+//    box's block order, so that blocks of small rank share K-blocks (FP16:
+//    hi/lo, one power-of-two scale per item and n-tile).
 //  * UD panel: per row tile (<= 64 rows of one target leaf) the A fragments
-//    [K-block over its segments][m-subtile]; segments are the z of every
-//    ancestor-level block, then x over each source leaf.
+//    [K-block over its segments][m-subtile]; segments are the z items of every
+//    ancestor (their blocks' U columns side by side, in the items' row order),
+//    then x over each source leaf.
 // ---------------------------------------------------------------------------
 struct MRChunk {
     int32_t row_begin;
@@ -181,13 +184,22 @@ struct MRVUnit {
     int64_t poff;         // offset of its partial sums (floats)
 };
 
-struct MRZItem {          // one low-rank block (t, s)
+struct MRZMember {        // one low-rank block (t, s) of a z item
     int32_t ubase;        // unit of column group 0 of (level, s)
     int32_t nu;           // units per column group
     int32_t vcol;         // first column of the block among the columns of (level, s)
     int32_t rank;
     float scale;          // product of the U and V scales
     int32_t col_off;      // FP8 forms: first of its `rank` per-column scales in zcol
+    int32_t row;          // first row of its z among the item's rows
+    int32_t pad_;
+};
+
+struct MRZItem {          // low-rank blocks of one target box: their z stacked, in shared K-blocks
+    int32_t m0;           // first member
+    int32_t nmem;         // members
+    int32_t rows;         // the members' ranks summed (at most 128)
+    int32_t pad_;
     int64_t zoff;         // first B fragment of its Zpack
 };
 
@@ -254,6 +266,7 @@ struct DevPlanMR {
     const MRLeaf *leaves;
     const MRVUnit *vunits;
     const MRZItem *zitems;
+    const MRZMember *zmembers;
     const MRSeg *segs;
     const MRTile *tiles;
     const MRTileGroup *tgroups;
@@ -320,7 +333,7 @@ struct BatchArgs {
     int32_t num_items;
     int32_t num_ctl;
     int32_t spin_limit;   // polls of a dependency wait before it flags an error and goes on
-    int32_t zs_rank;      // rows of the per-wave z scratch (multi-RHS members' largest rank)
+    int32_t zs_rank;      // rows of the per-wave z scratch (multi-RHS members' most z rows of an item)
 };
 
 // Kernel launchers (hmat_kernels.hip). Each returns a hipError_t as int.

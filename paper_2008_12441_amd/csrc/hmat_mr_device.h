@@ -9,9 +9,10 @@
 //   mr_vunit_group  per group of up to four units (a unit: level, source
 //              box, 64 V columns, up to 4 chunks): partial sums of V^T X,
 //              accumulated across the unit's chunks;
-//   mr_zitem   per low-rank block and n-tile: the fixed-order sum of its
-//              partials (Steps 2-4 collapsed), times the block's scales, packed
-//              as B fragments (FP16: with a power-of-two scale per n-tile);
+//   mr_zitem   per z item (the low-rank blocks of one target box) and n-tile:
+//              the fixed-order sum of each block's partials (Steps 2-4
+//              collapsed), times the block's scales, stacked and packed as B
+//              fragments (FP16: with a power-of-two scale per n-tile);
 //   mr_tile_group, mr_tile  per group of up to four row tiles of one chunk,
 //              or per row tile: Y over the z of every ancestor block and over
 //              x of every source leaf, written once.
@@ -587,8 +588,10 @@ __device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const fl
 }
 
 // ---------------------------------------------------------------------------
-// Partial reduction and z packing, one wave per (low-rank block, n-tile); zs
-// is the wave's LDS scratch of kMaxRankMR x 16 floats.
+// Partial reduction and z packing, one wave per (z item, n-tile): the z of the
+// item's blocks stacked in their rows, then packed as B fragments with one
+// power-of-two scale for the item and n-tile. zs is the wave's LDS scratch of
+// kMaxRankMR x 16 floats.
 // ---------------------------------------------------------------------------
 template <int STORE>
 __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, float (*zs)[16]) {
@@ -601,31 +604,40 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     const int n = nt * 16 + nn;
     const int64_t ustride = (int64_t)64 * ncol;
     float amax = 0.0f;
-    // lane group g sums columns g, g + 4, g + 8, ... of the block; four of them
-    // at a time, so that four independent loads are in flight per unit (the
-    // addresses of columns past the rank are clamped, their sums dropped)
-    for (int j0 = g; j0 < z.rank; j0 += 16) {
+    // Columns j0 + step q (q < 4) of member zm, four independent loads in flight
+    // per unit (the addresses of columns past the rank are clamped, their sums
+    // dropped); each sum runs over the units in order.
+    auto columns = [&](const MRZMember &zm, int j0, int step) {
         const float *src[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int j = j0 + 4 * q < z.rank ? j0 + 4 * q : z.rank - 1;
-            const int col = z.vcol + j;
-            src[q] = p.part + (z.ubase + (int64_t)(col >> 6) * z.nu) * ustride + (int64_t)(col & 63) * ncol + n;
+            const int j = j0 + step * q < zm.rank ? j0 + step * q : zm.rank - 1;
+            const int col = zm.vcol + j;
+            src[q] = p.part + (zm.ubase + (int64_t)(col >> 6) * zm.nu) * ustride + (int64_t)(col & 63) * ncol + n;
         }
         float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int i = 0; i < z.nu; ++i)
+        for (int i = 0; i < zm.nu; ++i)
 #pragma unroll
             for (int q = 0; q < 4; ++q) a[q] += src[q][(int64_t)i * ustride];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int j = j0 + 4 * q;
-            if (j < z.rank) {
-                float zsc = z.scale;
-                if constexpr (F::FP8) zsc = p.zcol[z.col_off + j];  // s_j of U times s_j of V
+            const int j = j0 + step * q;
+            if (j < zm.rank) {
+                float zsc = zm.scale;
+                if constexpr (F::FP8) zsc = p.zcol[zm.col_off + j];  // s_j of U times s_j of V
                 const float sj = a[q] * zsc;
-                zs[j][nn] = sj;
+                zs[zm.row + j][nn] = sj;
                 amax = fmaxf(amax, fabsf(sj));
             }
+        }
+    };
+    if (z.nmem == 1) {  // lane group g: columns g, g + 4, g + 8, ... of the block
+        const MRZMember zm = cload(p.zmembers, z.m0);
+        for (int j0 = g; j0 < zm.rank; j0 += 16) columns(zm, j0, 4);
+    } else {  // lane group g: blocks g, g + 4, ... of the item, four columns at a time
+        for (int mi = z.m0 + g; mi < z.m0 + z.nmem; mi += 4) {
+            const MRZMember zm = p.zmembers[mi];
+            for (int j0 = 0; j0 < zm.rank; j0 += 4) columns(zm, j0, 1);
         }
     }
     amax = wave_max(amax);
@@ -634,18 +646,19 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     const float inv = 1.0f / sig;
-    const int nkb = (z.rank + KB - 1) / KB;
+    const int nkb = (z.rows + KB - 1) / KB;
     for (int kb = 0; kb < nkb; ++kb) {
         float v[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int j = kb * KB + VW * g + e;
-            v[e] = j < z.rank ? zs[j][nn] * inv : 0.0f;
+            v[e] = j < z.rows ? zs[j][nn] * inv : 0.0f;
         }
         F::storeB(p.zpack, z.zoff + (int64_t)kb * p.ntmax + nt, lane, v);
     }
 }
 
+// ---------------------------------------------------------------------------
 // A chunk's step table held one entry per lane: lane l has the B offset (KiB)
 // and the segment of step w0 + l; the following 64 steps are loaded when a
 // window is entered and taken over when the next one is, so a step never

@@ -4,7 +4,7 @@
 // stream (bodies in hmat_mr_device.h): X packing (one workgroup per chunk and
 // n-tile: k_xpack_tile, or k_xpack for chunks of more than 512 rows), the
 // source side (k_vmfma_group: one workgroup per group of four V units over the
-// same chunks), z packing (k_zmfma: one wave per low-rank block and n-tile)
+// same chunks), z packing (k_zmfma: one wave per z item and n-tile)
 // and the target side (k_umfma_group: one workgroup per group of four row
 // tiles of a chunk; k_umfma, one wave per row tile, where a chunk's segments
 // or LDS needs exceed what the group kernel holds).
