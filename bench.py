@@ -436,11 +436,14 @@ def run_multi_rhs(stream, steps, warmup, with_oracle=True, method=None, forms=("
                      "phases_ms": [round(v, 5) for v in ph]}
         log(f"c3 {form}: {ms:.4f} ms per {k}-RHS product, {out[form]['GBps']} GB/s, {out[form]['TFLOPps']} TFLOP/s")
         h.close()
-    out["roofline"] = {"fp32": {"bound": "mfma", "peak": 157.3, "unit": "TFLOP/s",
-                                "frac": round(out["fp32"]["TFLOPps"] / 157.3, 4)}}
+    out["roofline"] = {}
+    if "fp32" in out:
+        out["roofline"]["fp32"] = {"bound": "mfma", "peak": 157.3, "unit": "TFLOP/s",
+                                   "frac": round(out["fp32"]["TFLOPps"] / 157.3, 4)}
     for form in forms:
         if form != "fp32":
-            out[f"{form}_speedup_vs_fp32"] = round(out["fp32"]["ms_per_step"] / out[form]["ms_per_step"], 3)
+            if "fp32" in out:
+                out[f"{form}_speedup_vs_fp32"] = round(out["fp32"]["ms_per_step"] / out[form]["ms_per_step"], 3)
             out["roofline"][form] = {"bound": "hbm", "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                      "frac": round(out[form]["GBps"] / HBM_PEAK_GBPS, 4)}
     out["counters"] = mr_counters("c3")
