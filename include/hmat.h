@@ -44,8 +44,11 @@ typedef enum hmat_status {
  * FP16 rounding the FP8 forms state). Accumulation is FP32 in every form. */
 typedef enum hmat_storage {
     HMAT_STORE_FP32 = 0,          /* D, U, V in FP32 */
-    HMAT_STORE_FP16_SCALED = 1,   /* D, U, V in FP16, one power-of-two scale per stored array
-                                     D_ts, U_ts, V_ts: s = 2^(ceil(log2 amax) - 15), q = RNE(v / s) */
+    HMAT_STORE_FP16_SCALED = 1,   /* D, U, V in FP16 with power-of-two scales
+                                     s = 2^(ceil(log2 amax) - 15), q = RNE(v / s): one per stored
+                                     U_ts and V_ts, and one per group of dense blocks D_ts (those
+                                     whose target leaves t have one parent and whose source leaves s
+                                     have one parent; amax over the group) */
     HMAT_STORE_BF16 = 2,          /* D, U, V in BF16, q = RNE(v), no scales */
     HMAT_STORE_FP8 = 3,           /* U, V in FP8 E4M3 (OCP E4M3FN) as a hi + lo pair per element with
                                      power-of-two scales per factor column j:
@@ -54,8 +57,8 @@ typedef enum hmat_storage {
                                        lo = RNE_e4m3(r / s'_j)  (all-zero columns: scale 1);
                                      the device multiplies with RNE_f16(hi + s'_j lo) (exact FP16
                                      conversions, one FP16 rounding) and folds s_j into z.
-                                     D in BF16: q = RNE_bf16(v / s) with the per-block power of two s
-                                     of the FP16 form, held as FP16 on the device (exact for
+                                     D in BF16: q = RNE_bf16(v / s) with the power of two s of the
+                                     FP16 form (the block's group), held as FP16 on the device (exact for
                                      |v / s| >= 2^-14). Multi-RHS handles (max_nrhs > 1) only. */
     HMAT_STORE_FP8_F16D = 4       /* U, V as in HMAT_STORE_FP8; D as in HMAT_STORE_FP16_SCALED */
 } hmat_storage;

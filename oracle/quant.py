@@ -1,7 +1,10 @@
 """Dequantised factor sets for the low-precision storage forms -- TEST INFRASTRUCTURE ONLY.
 
 Written independently of the GPU library's quantiser, from the storage rules:
-  fp16  one power-of-two scale per stored array (each D_ts, U_ts, V_ts):
+  fp16  one power-of-two scale per stored array of a low-rank block (each
+        U_ts, V_ts), and per group of dense blocks (the D_ts whose target leaves
+        t have one parent and whose source leaves s have one parent; amax over
+        the group):
         s = 2^(ceil(log2 amax) - 15), q = round-to-nearest-even(v / s) to IEEE
         half (numpy's float16 cast), dequantised value q * s (exact in FP32);
   bf16  q = round-to-nearest-even(v) to bfloat16 (torch's CPU cast);
@@ -10,7 +13,7 @@ Written independently of the GPU library's quantiser, from the storage rules:
         s' = the same power of two for amax(r), lo = E4M3 of r / s', and the
         value s * RNE_f16(hi + s' lo) (E4M3 = OCP E4M3FN, torch's
         float8_e4m3fn cast); dense blocks D as s * RNE_f16(BF16(v / s)) with
-        the fp16 form's per-block power of two s;
+        the fp16 form's power of two s for the block's group;
   fp8_f16d  U and V as in fp8, D as in fp16.
 """
 from __future__ import annotations
@@ -33,8 +36,13 @@ def fp16_scale(amax: float) -> float:
     return 2.0 ** max(c - 15, -126)
 
 
-def _dequant_fp16(a: np.ndarray) -> np.ndarray:
-    s = fp16_scale(float(np.max(np.abs(a))) if a.size else 0.0)
+def _amax(a: np.ndarray) -> float:
+    return float(np.max(np.abs(a))) if a.size else 0.0
+
+
+def _dequant_fp16(a: np.ndarray, amax: float | None = None) -> np.ndarray:
+    """FP16 values of a with the scale of amax (a's own largest |entry| by default)."""
+    s = fp16_scale(_amax(a) if amax is None else amax)
     q = (a.astype(np.float64) / s).astype(np.float32).astype(np.float16)
     return (q.astype(np.float64) * s).astype(np.float32)
 
@@ -91,10 +99,10 @@ def _dequant_fp8_columns(a: np.ndarray, rows: int, cols: int) -> np.ndarray:
     return (s * (hi + s2 * lo).astype(np.float16).astype(np.float64)).reshape(-1).astype(np.float32)
 
 
-def _dequant_dense_bf16_scaled(a: np.ndarray) -> np.ndarray:
+def _dequant_dense_bf16_scaled(a: np.ndarray, amax: float | None = None) -> np.ndarray:
     import torch
 
-    s = fp16_scale(float(np.max(np.abs(a))) if a.size else 0.0)
+    s = fp16_scale(_amax(a) if amax is None else amax)
     q = torch.from_numpy((a.astype(np.float64) / s).astype(np.float32)).to(torch.bfloat16).to(torch.float32)
     return (q.numpy().astype(np.float16).astype(np.float64) * s).astype(np.float32)
 
@@ -112,13 +120,23 @@ def dequantised(data, form: str):
     out = copy.copy(data)
     pool = data.pool.copy()
     sz = data.tree.end - data.tree.begin
+    parent = data.tree.parent
+    # a dense block's scale is that of its group: the dense blocks whose target
+    # and source leaves have the same parents as its own
+    group = {}
+    for b in range(len(data.blocks)):
+        if int(data.blocks.rank[b]) == 0:
+            t, s = int(data.blocks.target[b]), int(data.blocks.source[b])
+            oa = int(data.off_a[b])
+            key = (int(parent[t]), int(parent[s]))
+            group[key] = max(group.get(key, 0.0), _amax(data.pool[oa:oa + int(sz[t]) * int(sz[s])]))
     for b in range(len(data.blocks)):
         t, s, r = int(data.blocks.target[b]), int(data.blocks.source[b]), int(data.blocks.rank[b])
         m, n = int(sz[t]), int(sz[s])
         oa = int(data.off_a[b])
         if r == 0:
             dq = _dequant_dense_bf16_scaled if form == "fp8" else _dequant_fp16
-            pool[oa:oa + m * n] = dq(pool[oa:oa + m * n])
+            pool[oa:oa + m * n] = dq(pool[oa:oa + m * n], group[(int(parent[t]), int(parent[s]))])
         else:
             ob = int(data.off_b[b])
             if form == "fp16":

@@ -86,7 +86,6 @@ __device__ inline DevPlanMR load_plan_mr(const DevPlanMR *m) {
     HMAT_GLOBAL_FIELD(p, m, sz);
     HMAT_GLOBAL_FIELD(p, m, dscale);
     HMAT_GLOBAL_FIELD(p, m, chunks);
-    HMAT_GLOBAL_FIELD(p, m, leaves);
     HMAT_GLOBAL_FIELD(p, m, vunits);
     HMAT_GLOBAL_FIELD(p, m, zitems);
     HMAT_GLOBAL_FIELD(p, m, zmembers);

@@ -37,6 +37,7 @@ using hmat::Structure;
 using hmat::analyse_tree;
 using hmat::parallel_for;
 using hmat::validate_blocks;
+using hmat::dense_group_amax;
 using hmat::col_major_amax;
 using hmat::f32_to_bf16_rne;
 using hmat::f32_to_f16_rne;
@@ -209,13 +210,13 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
     if (storage != HMAT_STORE_FP32) {
         const bool scaled = storage == HMAT_STORE_FP16_SCALED;
         std::atomic<bool> ok{true};
+        std::vector<float> amax_d(nb, 0.0f);
         parallel_for(nb, [&](int64_t b) {
             bool fin = true;
             const hmat_block_desc &d = bl[b];
             const int64_t mt = t.size(d.target), ms = t.size(d.source);
             if (d.rank == 0) {
-                const float a = col_major_amax(d.a, mt, ms, d.lda, &fin);
-                if (scaled) hp.sD[b] = pow2_scale_f16(a);
+                amax_d[b] = col_major_amax(d.a, mt, ms, d.lda, &fin);
             } else {
                 const float au = col_major_amax(d.a, mt, d.rank, d.lda, &fin);
                 const float av = col_major_amax(d.b, ms, d.rank, d.ldb, &fin);
@@ -227,6 +228,11 @@ hmat_status build_plan(const Tree &t, const Structure &st, const hmat_block_desc
             if (!fin) ok = false;
         });
         if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
+        if (scaled) {  // a dense block's scale covers its group (see dense_group_amax)
+            dense_group_amax(t, bl, nb, amax_d);
+            for (int64_t b = 0; b < nb; ++b)
+                if (bl[b].rank == 0) hp.sD[b] = pow2_scale_f16(amax_d[b]);
+        }
     }
 
     // z layout: per non-leaf node t at depth 1..L-1, the z vectors of its low-rank blocks (t, s)
@@ -488,7 +494,7 @@ struct HostPlanMR {
     std::vector<int64_t> zmember_block;        // low-rank block of each z item member
     std::vector<std::vector<int32_t>> zrow_member;  // per z item: the member holding each row
     std::vector<hmat::MRSeg> segs;
-    std::vector<int32_t> seg_node;             // source leaf node of an x segment
+    std::vector<int32_t> seg_chunk;            // source chunk of an x segment (-1 for z)
     std::vector<hmat::MRTile> tiles;
     std::vector<hmat::MRTileGroup> tgroups;
     std::vector<hmat::MRUnitGroup> ugroups;
@@ -521,6 +527,15 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
     const int32_t nc = (int32_t)hp.chunk_node.size();
     hp.anc.assign((size_t)nc * (cd + 1), 0);
     std::vector<int32_t> cfirst(t.num_nodes, INT32_MAX), clast(t.num_nodes, -1), chunk_of(t.num_nodes, -1);
+    // the boxes at depth L - 1 whose leaves are the dense sources of a chunk's leaves (the
+    // chunk itself when the root is a leaf), in row order
+    auto dense_partners = [&](int32_t node) {
+        std::vector<int32_t> out;
+        if (L == 0) return std::vector<int32_t>{node};
+        for (int32_t ls : st.dense_src[node])
+            if (out.empty() || out.back() != t.parent[ls]) out.push_back(t.parent[ls]);
+        return out;
+    };
     for (int32_t c = 0; c < nc; ++c) {
         int32_t a = hp.chunk_node[c];
         chunk_of[a] = c;
@@ -536,13 +551,13 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
     hp.sD.assign(nb, 1.0f);
     if (half) {
         std::atomic<bool> ok{true};
+        std::vector<float> amax_d(nb, 0.0f);
         parallel_for(nb, [&](int64_t b) {
             bool fin = true;
             const hmat_block_desc &d = bl[b];
             const int64_t mt = t.size(d.target), ms = t.size(d.source);
             if (d.rank == 0) {
-                const float a = col_major_amax(d.a, mt, ms, d.lda, &fin);
-                if (f16) hp.sD[b] = pow2_scale_f16(a);
+                amax_d[b] = col_major_amax(d.a, mt, ms, d.lda, &fin);
             } else {
                 const float au = col_major_amax(d.a, mt, d.rank, d.lda, &fin);
                 const float av = col_major_amax(d.b, ms, d.rank, d.ldb, &fin);
@@ -554,6 +569,11 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             if (!fin) ok = false;
         });
         if (!ok) return fail(HMAT_ERR_INVALID_ARG, "factors contain non-finite values");
+        if (f16) {  // a dense block's scale covers its group (see dense_group_amax)
+            dense_group_amax(t, bl, nb, amax_d);
+            for (int64_t b = 0; b < nb; ++b)
+                if (bl[b].rank == 0) hp.sD[b] = pow2_scale_f16(amax_d[b]);
+        }
     }
     if (hp.fp8) {
         hp.colU.assign(nb, {});
@@ -567,45 +587,30 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
             e4m3_column_scales(d.b, t.size(d.source), d.rank, d.ldb, hp.colV[b].data());
         });
     }
-    // chunks and their leaves (K-block aligned)
+    // chunks: their rows are contiguous in the X fragments, padded once, at the chunk's end
     int64_t xf = 0;
     for (int32_t c = 0; c < nc; ++c) {
         const int32_t node = hp.chunk_node[c];
         hmat::MRChunk m{};
         m.row_begin = (int32_t)t.begin[node];
         m.rows = (int32_t)t.size(node);
+        m.nkb = (m.rows + KB - 1) / KB;
         m.leaf_base = (int32_t)hp.leaves.size();
         const std::vector<int32_t> lv = chunk_leaves(t, node);
-        const std::vector<int32_t> &src = L == 0 ? lv : st.dense_src[node];
+        const std::vector<int32_t> pn = dense_partners(node);
         m.nleaf = (int32_t)lv.size();
-        m.nsrc = (int32_t)src.size();
-        int32_t kb = 0;
+        m.nsrc = (int32_t)pn.size();
         for (int32_t lf : lv) {
-            hmat::MRLeaf e{(int32_t)t.begin[lf], (int32_t)t.size(lf), kb, (int32_t)((t.size(lf) + KB - 1) / KB)};
-            kb += e.nkb;
-            hp.leaves.push_back(e);
+            hp.leaves.push_back(hmat::MRLeaf{(int32_t)t.begin[lf], (int32_t)t.size(lf)});
             hp.leaf_node.push_back(lf);
         }
-        m.nkb = kb;
         m.xoff = xf;
-        xf += (int64_t)kb * hp.ntmax;
+        xf += (int64_t)m.nkb * hp.ntmax;
+        // one dense scale per partner box: the group of the dense blocks between the two (Def. 2.3
+        // makes every pair of a leaf of the chunk and a leaf of a partner a dense block)
         m.dscale_base = (int32_t)hp.dscale.size();
-        for (int32_t lt : lv)
-            for (int32_t ls : src) hp.dscale.push_back(hp.sD[L == 0 ? 0 : st.find(lt, ls)]);
+        for (int32_t q : pn) hp.dscale.push_back(hp.sD[L == 0 ? 0 : st.find(lv[0], t.kid(q, 0))]);
         hp.chunks.push_back(m);
-    }
-    // Source side: the chunk's rows need no leaf alignment there, so its X
-    // fragments are also kept with the rows contiguous and padded once, at the
-    // chunk's end. The two coincide when every leaf but the last is a whole
-    // number of K-blocks; otherwise every chunk gets the contiguous copy, after
-    // all the per-leaf ones, so that a unit's chunks stay consecutive.
-    bool aligned = true;
-    for (const hmat::MRChunk &m : hp.chunks)
-        for (int32_t lf = 0; lf + 1 < m.nleaf; ++lf) aligned = aligned && hp.leaves[m.leaf_base + lf].rows % KB == 0;
-    for (hmat::MRChunk &m : hp.chunks) {
-        m.nkbv = (m.rows + KB - 1) / KB;
-        m.xvoff = aligned ? m.xoff : xf;
-        if (!aligned) xf += (int64_t)m.nkbv * hp.ntmax;
     }
     hp.x_frags = xf;
     // V units: per level-l source box s and 64-column group, at most kUnitChunks chunks each
@@ -646,7 +651,7 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                     u.nc = std::min(kUnitChunks, c1 - u.c0);
                     u.nm = nm;
                     u.poff = (int64_t)hp.vunits.size() * 64 * hp.ntmax * 16;
-                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) af += (int64_t)hp.chunks[c].nkbv * nm;
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) af += (int64_t)hp.chunks[c].nkb * nm;
                     hp.vunits.push_back(u);
                     hp.unit_node.push_back(s);
                     hp.unit_group.push_back(g);
@@ -756,19 +761,19 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                 hmat::MRSeg sg{z.zoff, (z.rows + KB - 1) / KB, 0, zi, 0};
                 seg_kb += sg.nkb;
                 hp.segs.push_back(sg);
-                hp.seg_node.push_back(-1);
+                hp.seg_chunk.push_back(-1);
             }
         }
-        // x over each source leaf of the dense blocks, from the X fragments of the chunk holding it
-        const std::vector<int32_t> src = L == 0 ? chunk_leaves(t, hp.chunk_node[c]) : st.dense_src[hp.chunk_node[c]];
-        for (int32_t is = 0; is < m.nsrc; ++is) {
-            const int32_t sc = L == 0 ? c : chunk_of[t.parent[src[is]]];
+        // x over the rows of each partner box (the sources of the dense blocks), contiguous, from
+        // the X fragments of that chunk in contiguous row order
+        const std::vector<int32_t> pn = dense_partners(hp.chunk_node[c]);
+        for (int32_t ip = 0; ip < m.nsrc; ++ip) {
+            const int32_t sc = L == 0 ? c : chunk_of[pn[ip]];
             const hmat::MRChunk &ms = hp.chunks[sc];
-            const hmat::MRLeaf &e = hp.leaves[ms.leaf_base + (L == 0 ? 0 : t.child_pos[src[is]])];
-            hmat::MRSeg sg{ms.xoff + (int64_t)e.kb0 * hp.ntmax, e.nkb, 1, sc, is};
+            hmat::MRSeg sg{ms.xoff, ms.nkb, 1, sc, ip};
             seg_kb += sg.nkb;
             hp.segs.push_back(sg);
-            hp.seg_node.push_back(src[is]);
+            hp.seg_chunk.push_back(sc);
         }
         m.nseg = (int32_t)hp.segs.size() - m.seg_base;
         m.step_base = (int32_t)hp.ustep.size();
@@ -806,19 +811,18 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                 hp.ustep.push_back(e);
             }
         }
-        for (int32_t lf = 0; lf < m.nleaf; ++lf) {
-            const hmat::MRLeaf &e = hp.leaves[m.leaf_base + lf];
-            for (int32_t r0 = 0; r0 < e.rows; r0 += 64) {
-                hmat::MRTile tl{};
-                tl.aoff = uf;
-                tl.chunk = c;
-                tl.row0 = e.row_begin + r0;
-                tl.rows = std::min(64, e.rows - r0);
-                tl.nm = (tl.rows + 15) / 16;
-                tl.tleaf = lf;
-                uf += (int64_t)seg_kb * tl.nm;
-                hp.tiles.push_back(tl);
-            }
+        // row tiles: the chunk's rows, contiguous, 64 at a time (a tile may hold
+        // rows of several target leaves; their dense blocks share each source
+        // leaf's scale)
+        for (int32_t r0 = 0; r0 < m.rows; r0 += 64) {
+            hmat::MRTile tl{};
+            tl.aoff = uf;
+            tl.chunk = c;
+            tl.row0 = m.row_begin + r0;
+            tl.rows = std::min(64, m.rows - r0);
+            tl.nm = (tl.rows + 15) / 16;
+            uf += (int64_t)seg_kb * tl.nm;
+            hp.tiles.push_back(tl);
         }
     }
     hp.ud_frags = uf;
@@ -853,7 +857,7 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
         int64_t af = u.aoff;
         for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) {
             const hmat::MRChunk &m = hp.chunks[c];
-            for (int32_t kb = 0; kb < m.nkbv; ++kb)
+            for (int32_t kb = 0; kb < m.nkb; ++kb)
                 for (int32_t ms = 0; ms < u.nm; ++ms) {
                     T *fr = out + (af + (int64_t)kb * u.nm + ms) * 64 * vw;
                     for (int32_t l = 0; l < 64; ++l) {
@@ -882,7 +886,7 @@ void fill_v_mr(const Tree &t, const hmat_block_desc *bl, const HostPlanMR &hp, T
                             }
                     }
                 }
-            af += (int64_t)m.nkbv * u.nm;
+            af += (int64_t)m.nkb * u.nm;
         }
     });
 }
@@ -893,20 +897,45 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
     parallel_for((int64_t)hp.tiles.size(), [&](int64_t ti) {
         const hmat::MRTile &tl = hp.tiles[ti];
         const hmat::MRChunk &m = hp.chunks[tl.chunk];
-        const int32_t tnode = hp.leaf_node[m.leaf_base + tl.tleaf];
+        // the target leaf of each of the tile's rows, as an index into the tile's target leaves
+        std::vector<int32_t> tleaves, row_lt(tl.rows);
+        for (int32_t r = 0, lf = -1; r < tl.rows; ++r) {
+            while (lf + 1 < m.nleaf && tl.row0 + r >= hp.leaves[m.leaf_base + lf + 1].row_begin) ++lf;
+            if (tleaves.empty() || tleaves.back() != hp.leaf_node[m.leaf_base + lf])
+                tleaves.push_back(hp.leaf_node[m.leaf_base + lf]);
+            row_lt[r] = (int32_t)tleaves.size() - 1;
+        }
         int64_t af = tl.aoff;
         for (int32_t si = m.seg_base; si < m.seg_base + m.nseg; ++si) {
             const hmat::MRSeg &sg = hp.segs[si];
             const bool zseg = sg.kind == 0;
             // z segment: column kk is column kk - row of the member block holding
-            // row kk of the z item; x segment: column kk of the dense block
-            int64_t db = -1;
+            // row kk of the z item; x segment: column kk is row kk of the source
+            // chunk, a column of the dense block of the row's target leaf and the
+            // source leaf holding it
             int32_t ncols = 0;
+            std::vector<int32_t> col_ls, col_off;  // x: per column, the source leaf (index) and its column
+            std::vector<int64_t> blk;               // x: per (target leaf, source leaf) of the tile, the block
+            int32_t nls = 0;
+            float dsc = 1.0f;
             if (zseg) {
                 ncols = hp.zitems[sg.sidx].rows;
             } else {
-                db = (t.L == 0) ? 0 : st.find(tnode, hp.seg_node[si]);
-                ncols = (int32_t)t.size(hp.seg_node[si]);
+                const hmat::MRChunk &ms = hp.chunks[hp.seg_chunk[si]];
+                ncols = ms.rows;
+                col_ls.resize(ncols);
+                col_off.resize(ncols);
+                for (int32_t k = 0, lf = 0; k < ncols; ++k) {
+                    while (lf + 1 < ms.nleaf && ms.row_begin + k >= hp.leaves[ms.leaf_base + lf + 1].row_begin) ++lf;
+                    col_ls[k] = lf;
+                    col_off[k] = ms.row_begin + k - hp.leaves[ms.leaf_base + lf].row_begin;
+                }
+                nls = ms.nleaf;
+                blk.resize((size_t)tleaves.size() * nls);
+                for (size_t i = 0; i < tleaves.size(); ++i)
+                    for (int32_t j = 0; j < nls; ++j)
+                        blk[i * nls + j] = (t.L == 0) ? 0 : st.find(tleaves[i], hp.leaf_node[ms.leaf_base + j]);
+                dsc = hp.sD[blk[0]];  // the same for every block of the pair of boxes
             }
             const bool hilo = hp.fp8 && zseg;
             for (int32_t kb = 0; kb < sg.nkb; ++kb)
@@ -917,19 +946,22 @@ void fill_ud_mr(const Tree &t, const Structure &st, const hmat_block_desc *bl, c
                         uint8_t hi[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         for (int32_t e = 0; e < vw; ++e) {
                             const int32_t kk = kb * KB + vw * (l / 16) + e;
-                            int64_t b = db;
+                            int64_t b = -1;
                             int32_t col = kk;
                             if (zseg && kk < ncols) {
                                 const int32_t mi = hp.zrow_member[sg.sidx][kk];
                                 b = hp.zmember_block[mi];
                                 col = kk - hp.zmembers[mi].row;
                             }
-                            const float sc = kk >= ncols ? 1.0f : zseg ? hp.sU[b] : hp.sD[db];
+                            const float sc = kk >= ncols ? 1.0f : zseg ? hp.sU[b] : dsc;
                             float v = 0.0f;
                             if (tr < tl.rows && kk < ncols) {
+                                if (!zseg) {
+                                    b = blk[(size_t)row_lt[tr] * nls + col_ls[kk]];
+                                    col = col_off[kk];
+                                }
                                 const hmat_block_desc &d = bl[b];
-                                const int32_t rbase = (int32_t)(zseg ? t.begin[d.target] : t.begin[tnode]);
-                                v = d.a[(tl.row0 + tr - rbase) + (int64_t)col * d.lda];
+                                v = d.a[(tl.row0 + tr - t.begin[d.target]) + (int64_t)col * d.lda];
                             }
                             if (hilo) {
                                 if (kk < ncols) e4m3_hilo(v, hp.colU[b][2 * col], hp.colU[b][2 * col + 1], &hi[e], &lo[e]);
@@ -1042,7 +1074,6 @@ hmat_status upload_mr(hmat_handle *h, const Tree &t, const Structure &st, const 
     p.scales = p.sz;
     if ((s = upload(h, hp.dscale, &p.dscale)) != HMAT_OK) return s;
     if ((s = upload(h, hp.chunks, &p.chunks)) != HMAT_OK) return s;
-    if ((s = upload(h, hp.leaves, &p.leaves)) != HMAT_OK) return s;
     if ((s = upload(h, hp.vunits, &p.vunits)) != HMAT_OK) return s;
     if ((s = upload(h, hp.zitems, &p.zitems)) != HMAT_OK) return s;
     if ((s = upload(h, hp.zmembers, &p.zmembers)) != HMAT_OK) return s;
@@ -1195,7 +1226,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 int64_t bytes = 0;
                 for (int32_t i = g.u0; i < g.u0 + g.count; ++i) {
                     const hmat::MRVUnit &u = hpm.vunits[i];
-                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkbv * u.nm * 1024;
+                    for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkb * u.nm * 1024;
                 }
                 h->cost_src.push_back((float)bytes);
             }

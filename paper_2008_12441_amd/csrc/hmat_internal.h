@@ -127,52 +127,47 @@ struct DevPlan {
 //    A B fragment is KB inner indices x 16 columns with the mirrored lane
 //    mapping (lane l: column l % 16, inner indices VW * (l / 16) + [0, VW)),
 //    1 KiB for FP32, 2 KiB for FP16 (a high and a low half-precision part).
-//  * Target side: rows of every chunk are padded leaf by leaf to multiples of
-//    KB, so each leaf starts on a K-block boundary (a dense block's columns
-//    are one source leaf). Source side: a chunk's rows are taken contiguously
-//    and padded once, at the chunk's end (the same thing when every leaf but
-//    the last is a whole number of K-blocks).
+//  * Rows: a chunk's rows are taken contiguously and padded once, at the
+//    chunk's end, on both sides, whatever its leaves: the target side's row
+//    tiles run over the chunk's rows, and its dense part takes the rows of a
+//    partner box (the source leaves of the dense blocks, whose scale the pair
+//    of boxes shares) as one segment.
 //  * V panel: per unit (level, source box, 64-column group, up to 4 chunks of
 //    that box) the A fragments [chunk][K-block of its contiguous rows]
 //    [m-subtile]; a wave computes the unit's V^T X and writes its partial sums
 //    (64 x 16 NT floats).
-//  * Xpack: per chunk the B fragments [K-block][n-tile] of X in the leaf-padded
-//    row order, then (unless the two coincide) per chunk those of the
-//    contiguous row order; FP16: hi/lo with one power-of-two scale per chunk
-//    and n-tile of 16 columns, shared by both copies.
+//  * Xpack: per chunk the B fragments [K-block][n-tile] of X (FP16: hi/lo with
+//    one power-of-two scale per chunk and n-tile of 16 columns).
 //  * Zpack: per z item (the low-rank blocks of one target box, up to 128 rows
 //    of z in all) the B fragments [K-block][n-tile] of their z stacked in the
 //    box's block order, so that blocks of small rank share K-blocks (FP16:
 //    hi/lo, one power-of-two scale per item and n-tile).
-//  * UD panel: per row tile (<= 64 rows of one target leaf) the A fragments
+//  * UD panel: per row tile (<= 64 contiguous rows of one chunk) the A fragments
 //    [K-block over its segments][m-subtile]; segments are the z items of every
 //    ancestor (their blocks' U columns side by side, in the items' row order),
-//    then x over each source leaf.
+//    then x over the rows of each partner box.
 // ---------------------------------------------------------------------------
 struct MRChunk {
     int32_t row_begin;
     int32_t rows;
-    int32_t nkb;          // K-blocks of its leaf-padded rows (the target-side x segments)
-    int32_t leaf_base;    // first entry in the leaf table
+    int32_t nkb;          // K-blocks of its rows, contiguous and padded once, at the end
+    int32_t leaf_base;    // first entry in the host's leaf table
     int32_t nleaf;        // its leaves (the target leaves of its rows)
     int32_t seg_base;     // first U-phase segment
     int32_t nseg;
-    int32_t dscale_base;  // nleaf x nsrc dense-block scales
+    int32_t dscale_base;  // nsrc dense scales, one per partner box
     int64_t xoff;         // first B fragment of its Xpack (relative to xpack)
     int32_t step_base;    // first entry of its U-phase step table
     int32_t nsteps;       // K-block steps over all its segments
     int32_t ulo_base;     // FP8 forms: first of its 32 x nzsteps U lo-scales in ulo
     int32_t nzsteps;      // steps over z segments (they come first)
-    int32_t nsrc;         // source leaves of its dense blocks
-    int32_t nkbv;         // K-blocks of its rows taken contiguously (the source-side contraction)
-    int64_t xvoff;        // first B fragment of those (relative to xpack): xoff when the two coincide
+    int32_t nsrc;         // partner boxes of its dense blocks (one x segment each)
+    int32_t pad_;
 };
 
-struct MRLeaf {
+struct MRLeaf {           // host side: a chunk's leaf
     int32_t row_begin;    // global first row
     int32_t rows;
-    int32_t kb0;          // first K-block inside the chunk's padded rows
-    int32_t nkb;
 };
 
 struct MRVUnit {
@@ -207,8 +202,8 @@ struct MRSeg {
     int64_t src;          // first B fragment (Zpack or Xpack)
     int32_t nkb;          // K-blocks
     int32_t kind;         // 0: z of a block, 1: x over a source leaf
-    int32_t sidx;         // block id (z) or chunk id (x, the chunk holding the leaf): scale row
-    int32_t leaf;         // x: index of the leaf among the chunk's dense sources
+    int32_t sidx;         // z item (z) or the partner box's chunk (x): scale row
+    int32_t leaf;         // x: index of the partner box among the chunk's (its dense scale)
 };
 
 struct MRTile {
@@ -217,8 +212,7 @@ struct MRTile {
     int32_t row0;         // global first row
     int32_t rows;         // valid rows (<= 64)
     int32_t nm;           // m-subtiles
-    int32_t tleaf;        // target leaf index in the chunk
-    int32_t pad_;
+    int32_t pad_[2];
 };
 
 struct MRTileGroup {      // up to four consecutive row tiles of one chunk, run by one workgroup
@@ -263,7 +257,6 @@ struct DevPlanMR {
     float *sz;                // per block x ntmax n-tile scales of Zpack
     const float *dscale;
     const MRChunk *chunks;
-    const MRLeaf *leaves;
     const MRVUnit *vunits;
     const MRZItem *zitems;
     const MRZMember *zmembers;

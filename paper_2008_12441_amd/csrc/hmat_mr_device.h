@@ -428,8 +428,7 @@ __device__ inline void mfma_steps(const void *A, const void *B, int64_t af0, int
 // 16 nt + l % 16, which is where they sit in the fragment. The first four
 // K-blocks of every wave stay in registers between the amax and the split, so
 // a chunk of up to 16 K-blocks (512 rows in FP16) reads X once; the rest of a
-// longer chunk is read a second time. Where the chunk's leaves are not whole
-// K-blocks, the source side's copy (rows contiguous) is written as well.
+// longer chunk is read a second time.
 // ---------------------------------------------------------------------------
 template <int STORE>
 __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx, int k,
@@ -442,20 +441,13 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = nt * 16 + (lane & 15);
-    const float *col = x + (int64_t)n * ldx;
-    // the leaf holding K-block kb (leaves start on K-block boundaries)
-    auto leaf_of = [&](int kb) {
-        int lf = 0;
-        while (lf + 1 < ch.nleaf && cload(p.leaves, ch.leaf_base + lf + 1).kb0 <= kb) ++lf;
-        return cload(p.leaves, ch.leaf_base + lf);
-    };
-    auto gather = [&](int kb, float (&v)[VW]) {  // zero past the leaf's rows and past column k
-        const MRLeaf L = leaf_of(kb);
-        const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
+    const float *col = x + (int64_t)n * ldx + ch.row_begin;
+    auto gather = [&](int kb, float (&v)[VW]) {  // zero past the chunk's rows and past column k
+        const int off0 = kb * KB + VW * (lane >> 4);
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int o = off0 + e;
-            v[e] = (n < k && o < L.rows) ? col[L.row_begin + o] : 0.0f;
+            v[e] = (n < k && o < ch.rows) ? col[o] : 0.0f;
         }
     };
     auto store = [&](int kb, const float (&v)[VW], float inv) {
@@ -502,17 +494,6 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
         gather(kb, t);
         store(kb, t, inv);
     }
-    if (ch.xvoff != ch.xoff)  // the source side's copy: the chunk's rows contiguous
-        for (int kb = wave; kb < ch.nkbv; kb += 4) {
-            const int off0 = kb * KB + VW * (lane >> 4);
-            float t[VW];
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                const int o = off0 + e;
-                t[e] = (n < k && o < ch.rows) ? col[ch.row_begin + o] * inv : 0.0f;
-            }
-            F::storeB(p.xpack, ch.xvoff + (int64_t)kb * p.ntmax + nt, lane, t);
-        }
 }
 
 // ---------------------------------------------------------------------------
@@ -565,26 +546,14 @@ __device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const fl
         inv = 1.0f / sc;
     }
     const int j = lane & 15;
+    const float *src = tile + j * rs;
     for (int kb = wave; kb < ch.nkb; kb += 4) {
-        int lf = 0;  // the leaf holding K-block kb (leaves start on K-block boundaries)
-        while (lf + 1 < ch.nleaf && cload(p.leaves, ch.leaf_base + lf + 1).kb0 <= kb) ++lf;
-        const MRLeaf L = cload(p.leaves, ch.leaf_base + lf);
-        const int off0 = (kb - L.kb0) * KB + VW * (lane >> 4);
-        const float *src = tile + j * rs + (L.row_begin - ch.row_begin);
+        const int off0 = kb * KB + VW * (lane >> 4);
         float t[VW];
 #pragma unroll
-        for (int e = 0; e < VW; ++e) t[e] = off0 + e < L.rows ? src[off0 + e] * inv : 0.0f;
+        for (int e = 0; e < VW; ++e) t[e] = off0 + e < ch.rows ? src[off0 + e] * inv : 0.0f;
         F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, t);
     }
-    if (ch.xvoff != ch.xoff)  // the source side's copy: the chunk's rows contiguous
-        for (int kb = wave; kb < ch.nkbv; kb += 4) {
-            const int off0 = kb * KB + VW * (lane >> 4);
-            const float *src = tile + j * rs;
-            float t[VW];
-#pragma unroll
-            for (int e = 0; e < VW; ++e) t[e] = off0 + e < ch.rows ? src[off0 + e] * inv : 0.0f;
-            F::storeB(p.xpack, ch.xvoff + (int64_t)kb * p.ntmax + nt, lane, t);
-        }
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +657,7 @@ struct StepWindow {
 };
 
 // ---------------------------------------------------------------------------
-// Target side, one wave per row tile (<= 64 rows of one target leaf): Y over
+// Target side, one wave per row tile (<= 64 contiguous rows of a chunk): Y over
 // the z of every ancestor block and over x of every source leaf, written once.
 // ---------------------------------------------------------------------------
 template <int STORE, int NT, bool LANE_SCALES>
@@ -709,7 +678,7 @@ __device__ inline void mr_tile(const DevPlanMR &p, int w, int lane, int k, float
     // A fragments are contiguous over the tile's steps; the chunk's step
     // table gives each step's B fragment (z of a block, or x of a source leaf).
     const MRStep *steps = p.ustep + ch.step_base;
-    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;  // this target leaf's dense scales
+    const float *drow = p.dscale + ch.dscale_base;  // the dense scale of each source leaf
     // LANE_SCALES (at most 64 segments): per lane j, segment j's n-tile scales,
     // its dense factor and kind; per lane l, step w0 + l of a window of 64
     // steps (its B offset in KiB and its segment). A step then reads them with
@@ -938,7 +907,7 @@ __device__ inline void mr_tile_group(const DevPlanMR &p, int g, int k, float alp
 #pragma unroll
     for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
     const MRStep *steps = p.ustep + ch.step_base;
-    const float *drow = p.dscale + ch.dscale_base + tl.tleaf * ch.nsrc;
+    const float *drow = p.dscale + ch.dscale_base;
     float fv = 1.0f;
     int vk = 0;
     if (lane < ch.nseg) {  // per lane j: segment j's n-tile scales (dense factor folded in) and kind
@@ -1025,10 +994,10 @@ __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *
 #pragma unroll
     for (int t = 0; t < NT; ++t) scur[t] = sv[t] = 1.0f;
     int nsteps = 0;
-    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkbv;
+    for (int c = u.c0; c < u.c0 + u.nc; ++c) nsteps += cload(p.chunks, c).nkb;
     int vn = 0;  // lane j: K-blocks of the unit's chunk j
     if (lane < u.nc) {
-        vn = p.chunks[u.c0 + lane].nkbv;
+        vn = p.chunks[u.c0 + lane].nkb;
         if (F::SCALED)
 #pragma unroll
             for (int t = 0; t < NT; ++t) sv[t] = p.sx[(int64_t)(u.c0 + lane) * p.ntmax + t];
@@ -1054,7 +1023,7 @@ __device__ inline void mr_vunit_group(const DevPlanMR &p, int g, unsigned char *
             return a;
         }
     };
-    const int64_t b0 = cload(p.chunks, u.c0).xvoff, ntm = p.ntmax;
+    const int64_t b0 = cload(p.chunks, u.c0).xoff, ntm = p.ntmax;
     constexpr int64_t bbytes = 16 * F::BFRAG;
     auto bofs_of = [&](int st) -> int64_t { return (b0 + (int64_t)st * ntm) * bbytes; };
     int c = 0, cend = 0;  // chunk (index in the unit) of the step asked for last, and the step where it ends

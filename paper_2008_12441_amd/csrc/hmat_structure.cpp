@@ -179,4 +179,16 @@ hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb
     return HMAT_OK;
 }
 
+void dense_group_amax(const Tree &t, const hmat_block_desc *bl, int64_t nb, std::vector<float> &amax) {
+    std::unordered_map<uint64_t, float> group;  // (parent of the target, parent of the source) -> largest |entry|
+    auto key = [&](int64_t b) { return Structure::key(t.parent[bl[b].target], t.parent[bl[b].source]); };
+    for (int64_t b = 0; b < nb; ++b)
+        if (bl[b].rank == 0) {
+            float &g = group[key(b)];
+            g = std::max(g, amax[b]);
+        }
+    for (int64_t b = 0; b < nb; ++b)
+        if (bl[b].rank == 0) amax[b] = group[key(b)];
+}
+
 }  // namespace hmat

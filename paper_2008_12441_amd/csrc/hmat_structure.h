@@ -80,4 +80,12 @@ struct Structure {
 // and index them.
 hmat_status validate_blocks(const Tree &t, const hmat_block_desc *bl, int64_t nb, Structure &st);
 
+// The scaled storage forms give the dense blocks one power-of-two scale per
+// group: the dense blocks whose target leaves have one parent and whose source
+// leaves have one parent (the near field between two boxes at depth L - 1).
+// amax holds each dense block's largest |entry| (the entries of low-rank
+// blocks are left alone); on return a dense block's entry holds the largest
+// over its group.
+void dense_group_amax(const Tree &t, const hmat_block_desc *bl, int64_t nb, std::vector<float> &amax);
+
 }  // namespace hmat

@@ -12,15 +12,18 @@ by routes that share nothing with it:
     a logarithm: s = 2^(E - 15) for the smallest E with amax <= 2^E, at least
     2^-126, and 1 for an all-zero array;
   * the per-block dispatch of ``dequantised`` is checked array by array: one
-    scale per stored array in the FP16 form, the dense blocks of the FP8 form
+    scale per stored U or V array in the FP16 form and one per group of dense
+    blocks (those whose target leaves have one parent and whose source leaves
+    have one parent, the groups found here from the tree), the dense blocks of the FP8 form
     through BF16 of v / s and those of the FP8 + FP16 D form through the FP16
     rule, and U and V per column in both FP8 forms;
   * the library's host quantiser (compiled from its source into the probe)
     reproduces the oracle's FP16 and BF16-of-scaled values bit for bit.
 
 Planted mistakes (a wrong scale exponent, D through the wrong rule, a scale
-per column instead of per array, BF16 by truncation, FP16 by truncation) are
-made in a copy of the oracle's source and each must fail one of these pins.
+per column instead of per array, a dense block's own scale instead of its
+group's, BF16 by truncation, FP16 by truncation) are made in a copy of the
+oracle's source and each must fail one of these pins.
 """
 import copy
 import os
@@ -68,9 +71,12 @@ def scale_rule(amax: float) -> float:
     return float(np.ldexp(1.0, max(big_e - 15, -126)))
 
 
-def ref_fp16_array(a):
+def ref_fp16_array(a, amax=None):
+    """FP16 values of a with the scale of amax (a's own largest |entry| by default)."""
     a = np.asarray(a, dtype=np.float32)
-    s = scale_rule(float(np.max(np.abs(a)))) if a.size else 1.0
+    if amax is None:
+        amax = float(np.max(np.abs(a))) if a.size else 0.0
+    s = scale_rule(amax)
     return (rne_f16(a.astype(np.float64) / s) * s).astype(np.float32)
 
 
@@ -78,10 +84,29 @@ def ref_bf16(a):
     return rne_bf16(np.asarray(a, dtype=np.float32).astype(np.float64)).astype(np.float32)
 
 
-def ref_dense_bf16_scaled(a):
+def ref_dense_bf16_scaled(a, amax=None):
     a = np.asarray(a, dtype=np.float32)
-    s = scale_rule(float(np.max(np.abs(a)))) if a.size else 1.0
+    if amax is None:
+        amax = float(np.max(np.abs(a))) if a.size else 0.0
+    s = scale_rule(amax)
     return (rne_f16(rne_bf16(a.astype(np.float64) / s)) * s).astype(np.float32)
+
+
+def dense_groups(data):
+    """Per dense block, the largest |entry| over its group: the dense blocks whose
+    target leaf is a child of the same box as its own, and whose source leaf is."""
+    sz = data.tree.end - data.tree.begin
+    par = data.tree.parent
+    dense = [b for b in range(len(data.blocks)) if int(data.blocks.rank[b]) == 0]
+    out = {}
+    for b in dense:
+        t, s = int(data.blocks.target[b]), int(data.blocks.source[b])
+        mates = [c for c in dense if int(par[int(data.blocks.source[c])]) == int(par[s]) and
+                 int(par[int(data.blocks.target[c])]) == int(par[t])]
+        out[b] = max(float(np.max(np.abs(data.pool[int(data.off_a[c]):int(data.off_a[c]) +
+                                                   int(sz[data.blocks.target[c]]) *
+                                                   int(sz[data.blocks.source[c]])]))) for c in mates)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -201,6 +226,7 @@ def _check_block_arrays(q, form):
     out = q.dequantised(data, form)
     assert out is not data and out.pool is not data.pool
     sz = data.tree.end - data.tree.begin
+    gmax = dense_groups(data)
     for b in range(len(data.blocks)):
         r = int(data.blocks.rank[b])
         m, n = int(sz[data.blocks.target[b]]), int(sz[data.blocks.source[b]])
@@ -211,9 +237,9 @@ def _check_block_arrays(q, form):
             if form == "bf16":
                 ref = ref_bf16(src)
             elif form == "fp8":
-                ref = ref_dense_bf16_scaled(src)
+                ref = ref_dense_bf16_scaled(src, gmax[b])
             else:
-                ref = ref_fp16_array(src)
+                ref = ref_fp16_array(src, gmax[b])             # one scale for the block's group
             assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"{form}: dense block {b}"
             continue
         ob = int(data.off_b[b])
@@ -257,13 +283,22 @@ def test_pin(name):
 
 def test_scale_granularity_is_observable():
     """The test set distinguishes a scale per array from one per column: with
-    per-column scales, some U entries would take a different value."""
+    per-column scales, some U entries would take a different value; and a dense
+    block's own scale from its group's: some groups mix magnitudes."""
     data = lowrank_test_set()
     b = int(np.nonzero(data.blocks.rank > 0)[0][0])
     u = data.u(b)
     per_array = ref_fp16_array(np.asfortranarray(u).reshape(-1, order="F"))
     per_col = np.concatenate([ref_fp16_array(u[:, j]) for j in range(u.shape[1])])
     assert not np.array_equal(per_array, per_col)
+    gmax = dense_groups(data)
+    sz = data.tree.end - data.tree.begin
+    differ = 0
+    for d, g in gmax.items():
+        oa, m, n = int(data.off_a[d]), int(sz[data.blocks.target[d]]), int(sz[data.blocks.source[d]])
+        a = data.pool[oa:oa + m * n]
+        differ += not np.array_equal(ref_fp16_array(a), ref_fp16_array(a, g))
+    assert differ > 0
 
 
 # ---------------------------------------------------------------------------
@@ -315,6 +350,10 @@ MUTANTS = {
                             "dq = _dequant_fp16")],
     "fp8_f16d_dense_via_bf16": [('dq = _dequant_dense_bf16_scaled if form == "fp8" else _dequant_fp16',
                                  "dq = _dequant_dense_bf16_scaled")],
+    "dense_scale_per_block": [("pool[oa:oa + m * n] = dq(pool[oa:oa + m * n], group[(int(parent[t]), int(parent[s]))])",
+                               "pool[oa:oa + m * n] = dq(pool[oa:oa + m * n])")],
+    "dense_group_per_source_leaf": [("key = (int(parent[t]), int(parent[s]))", "key = (int(parent[t]), s)"),
+                                    ("group[(int(parent[t]), int(parent[s]))]", "group[(int(parent[t]), s)]")],
     "fp16_scale_per_column": [
         ("pool[oa:oa + m * r] = _dequant_fp16(pool[oa:oa + m * r])",
          "pool[oa:oa + m * r] = np.concatenate([_dequant_fp16(c) for c in np.split(pool[oa:oa + m * r], r)])")],
