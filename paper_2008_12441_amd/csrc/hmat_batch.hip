@@ -147,16 +147,8 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
         }
         if (HAS_M && it.kind >= BK_MX) {
             const DevPlanMR p = load_plan_mr(&a.members[it.member].mp);
-            if (it.kind == BK_MX) {
-                float *tile = reinterpret_cast<float *>(lds);
-                for (int j = 0; j < it.count; ++j) {
-                    if (j) __syncthreads();  // the tile and the maxima are reused
-                    if (p.max_chunk_rows <= kXpackMaxRows)  // coalesced, through an LDS tile
-                        mr_xpack_tile<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, tile,
-                                             tile + 16 * (p.max_chunk_rows + 1));
-                    else
-                        mr_xpack<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, tile);
-                }
+            if (it.kind == BK_MX) {  // a wave per chunk
+                for (int j = wave; j < it.count; j += 4) mr_xpack_wave<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, lane);
             } else if (it.kind == BK_MV) {  // unit groups, X fragments shared through the LDS ring
                 for (int j = 0; j < it.count; ++j) mr_vunit_group<STORE, 1>(p, it.first + j, lds);
             } else if (it.kind == BK_MZ) {

@@ -133,7 +133,8 @@ std::vector<Costed> member_items(const hmat_batch_handle *b, int32_t i, double g
     } else {
         const hmat::DevPlanMR &p = h->mrp;
         std::vector<float> xcost(p.num_chunks);
-        for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2 + 16384.0f;
+        // X read and fragments written, plus a round trip shared by the four chunks a workgroup packs at once
+        for (int32_t c = 0; c < p.num_chunks; ++c) xcost[c] = (float)h->chunk_rows[c] * 16 * 4 * 2 + 4096.0f;
         const int32_t nmx = stage(hmat::BK_MX, p.num_chunks, xcost, -1, 0, c0);
         const int32_t nmv = stage(hmat::BK_MV, p.num_ugroups, h->cost_src, c0, nmx, c0 + 1);
         const int32_t nmz = stage(hmat::BK_MZ, p.num_zitems, h->cost_z1, nmv ? c0 + 1 : c0, nmv ? nmv : nmx, c0 + 2);

@@ -811,15 +811,17 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
                 hp.ustep.push_back(e);
             }
         }
-        // row tiles: the chunk's rows, contiguous, 64 at a time (a tile may hold
-        // rows of several target leaves; their dense blocks share each source
-        // leaf's scale)
-        for (int32_t r0 = 0; r0 < m.rows; r0 += 64) {
+        // row tiles: the chunk's rows, contiguous, in four tiles per started 256
+        // rows (so that a chunk of a few dozen rows still keeps the four waves of
+        // a tile group busy), each a whole number of 16-row subtiles, at most 64;
+        // a tile may hold rows of several target leaves
+        const int32_t th = std::min(64, ((m.rows + 4 * ((m.rows + 255) / 256) - 1) / (4 * ((m.rows + 255) / 256)) + 15) / 16 * 16);
+        for (int32_t r0 = 0; r0 < m.rows; r0 += th) {
             hmat::MRTile tl{};
             tl.aoff = uf;
             tl.chunk = c;
             tl.row0 = m.row_begin + r0;
-            tl.rows = std::min(64, m.rows - r0);
+            tl.rows = std::min(th, m.rows - r0);
             tl.nm = (tl.rows + 15) / 16;
             uf += (int64_t)seg_kb * tl.nm;
             hp.tiles.push_back(tl);
@@ -1221,9 +1223,11 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 h->max_nseg = std::max(h->max_nseg, c.nseg);
             }
             // per unit group and tile group: the A fragments its waves stream (the B
-            // sequence they share is read once)
+            // sequence they share is read once), plus kGroupBytes for the latency of
+            // its start (step table, first fragments) and end (y or partials)
+            constexpr int64_t kGroupBytes = 32768;
             for (const hmat::MRUnitGroup &g : hpm.ugroups) {
-                int64_t bytes = 0;
+                int64_t bytes = kGroupBytes;
                 for (int32_t i = g.u0; i < g.u0 + g.count; ++i) {
                     const hmat::MRVUnit &u = hpm.vunits[i];
                     for (int32_t c = u.c0; c < u.c0 + u.nc; ++c) bytes += (int64_t)hpm.chunks[c].nkb * u.nm * 1024;
@@ -1231,7 +1235,7 @@ hmat_status create_impl(const hmat_tree_desc *tree, const hmat_block_desc *block
                 h->cost_src.push_back((float)bytes);
             }
             for (const hmat::MRTileGroup &g : hpm.tgroups) {
-                int64_t bytes = 0;
+                int64_t bytes = kGroupBytes;
                 for (int32_t i = g.tile0; i < g.tile0 + g.ntiles; ++i)
                     bytes += (int64_t)hpm.chunks[g.chunk].nsteps * hpm.tiles[i].nm * 1024;
                 h->cost_tgt.push_back((float)bytes);

@@ -285,7 +285,7 @@ enum BKind : int32_t {
     BK_SZ1 = 1,  // single vector: stage-1 reduction items (a wave each)
     BK_SZ2 = 2,  // single vector: stage-2 reduction items (a wave each)
     BK_SU = 3,   // single vector: chunks (the whole workgroup each)
-    BK_MX = 4,   // multi-RHS: X packing of chunks (the whole workgroup each)
+    BK_MX = 4,   // multi-RHS: X packing of chunks (a wave each)
     BK_MV = 5,   // multi-RHS: V units (a wave each)
     BK_MZ = 6,   // multi-RHS: z items (a wave each)
     BK_MU = 7    // multi-RHS: row tiles (a wave each)

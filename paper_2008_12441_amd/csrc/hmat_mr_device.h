@@ -497,6 +497,75 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
 }
 
 // ---------------------------------------------------------------------------
+// The same packing by one wave per (chunk, n-tile), for the batched kernel,
+// whose chunks are mostly a few hundred rows or less: the four waves of a
+// workgroup pack four chunks at once instead of one after the other. The
+// first 128 rows stay in registers between the maximum and the split; the rest
+// of a longer chunk is read a second time (from L2, as a rule). The fragments and the scale are the
+// ones mr_xpack and mr_xpack_tile write.
+// ---------------------------------------------------------------------------
+template <int STORE>
+__device__ inline void mr_xpack_wave(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx,
+                                     int k, int lane) {
+    using F = MR<STORE>;
+    constexpr int VW = F::VW;
+    constexpr int KB = F::KB;
+    constexpr int R = 128 / KB;  // K-blocks held in registers
+    const MRChunk ch = cload(p.chunks, c);
+    const int n = nt * 16 + (lane & 15);
+    const float *col = x + (int64_t)n * ldx + ch.row_begin;
+    auto gather = [&](int kb, float (&v)[VW]) {  // zero past the chunk's rows and past column k
+        const int off0 = kb * KB + VW * (lane >> 4);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int o = off0 + e;
+            v[e] = (n < k && o < ch.rows) ? col[o] : 0.0f;
+        }
+    };
+    auto store = [&](int kb, const float (&v)[VW], float inv) {
+        float t[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) t[e] = v[e] * inv;
+        F::storeB(p.xpack, ch.xoff + (int64_t)kb * p.ntmax + nt, lane, t);
+    };
+    float v[R][VW];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r < ch.nkb) {
+            gather(r, v[r]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[r][e] = 0.0f;
+        }
+    }
+    float inv = 1.0f;
+    if (F::SCALED) {
+        float m = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) m = fmaxf(m, fabsf(v[r][e]));
+        for (int kb = R; kb < ch.nkb; ++kb) {
+            float t[VW];
+            gather(kb, t);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) m = fmaxf(m, fabsf(t[e]));
+        }
+        const float s = col_scale(wave_max(m));
+        if (lane == 0) p.sx[(int64_t)c * p.ntmax + nt] = s;
+        inv = 1.0f / s;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < ch.nkb) store(r, v[r], inv);
+    for (int kb = R; kb < ch.nkb; ++kb) {
+        float t[VW];
+        gather(kb, t);
+        store(kb, t, inv);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The same packing for chunks of at most 512 rows, with X read coalesced: each
 // wave reads four of the 16 columns, 64 consecutive rows per instruction, into
 // an LDS tile (16 x (rows + 1) floats, the padding spreads the banks), and the
@@ -573,9 +642,9 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     const int n = nt * 16 + nn;
     const int64_t ustride = (int64_t)64 * ncol;
     float amax = 0.0f;
-    // Columns j0 + step q (q < 4) of member zm, four independent loads in flight
-    // per unit (the addresses of columns past the rank are clamped, their sums
-    // dropped); each sum runs over the units in order.
+    // Columns j0 + step q (q < 4) of member zm, the loads of four columns and
+    // four units in flight (the addresses of columns past the rank are clamped,
+    // their sums dropped); each sum runs over the units in order.
     auto columns = [&](const MRZMember &zm, int j0, int step) {
         const float *src[4];
 #pragma unroll
@@ -585,9 +654,21 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
             src[q] = p.part + (zm.ubase + (int64_t)(col >> 6) * zm.nu) * ustride + (int64_t)(col & 63) * ncol + n;
         }
         float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int i = 0; i < zm.nu; ++i)
+        int i0 = 0;
+        for (; i0 + 4 <= zm.nu; i0 += 4) {  // four units' loads, then their sums in order
+            float t[4][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] += src[q][(int64_t)i * ustride];
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[u][q] = src[q][(int64_t)(i0 + u) * ustride];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] += t[u][q];
+        }
+        for (; i0 < zm.nu; ++i0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] += src[q][(int64_t)i0 * ustride];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = j0 + step * q;
@@ -612,7 +693,9 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
     amax = wave_max(amax);
     const float sig = F::SCALED ? col_scale(amax) : 1.0f;
     if (F::SCALED && lane == 0) p.sz[(int64_t)item * p.ntmax + nt] = sig;
-    __builtin_amdgcn_s_waitcnt(0);
+    // the wave's LDS writes above precede its reads below: a wave's LDS operations run in order, so
+    // only the compiler has to keep them so
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const float inv = 1.0f / sig;
     const int nkb = (z.rows + KB - 1) / KB;
@@ -778,6 +861,8 @@ __device__ inline void static_for(Fn &&f) {
 // registers, KS staging sets for B. The 16-bit forms from NT = 4 up use three
 // and one, which keeps them within 256 registers at NT > 4 (two waves per
 // SIMD) and within 168 at NT = 4 (three).
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
 template <int STORE, int NT>
 struct GroupDepth {
     static constexpr bool lean = STORE != HMAT_STORE_FP32 && NT >= 4;
@@ -791,7 +876,7 @@ __device__ inline void mfma_steps_group(const void *A, int64_t af0, int nm, cons
                                         f32x4 (&acc)[4][NT], const float (&scur)[NT], const float (&sv)[NT]) {
     using F = MR<STORE>;
     constexpr int KA = GroupDepth<STORE, NT>::KA, KS = GroupDepth<STORE, NT>::KS;
-    constexpr int U = KA * KS / (KA % 2 == 0 && KS == 2 ? 2 : 1);  // lcm(KA, KS) for KS in {1, 2}
+    constexpr int U = KA * KS / cgcd(KA, KS);  // lcm(KA, KS)
     constexpr int kUnits = NT * F::BFRAG;  // 16-byte pieces of one step's B
     constexpr int kSlot = kUnits * 16;
     constexpr int kPer = (kUnits + 255) / 256;
