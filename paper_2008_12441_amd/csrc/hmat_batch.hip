@@ -147,13 +147,31 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
         }
         if (HAS_M && it.kind >= BK_MX) {
             const DevPlanMR p = load_plan_mr(&a.members[it.member].mp);
-            if (it.kind == BK_MX) {  // a wave per chunk
-                for (int j = wave; j < it.count; j += 4) mr_xpack_wave<STORE>(p, it.first + j, 0, ar.x, ar.ldx, k, lane);
+            if (it.kind == BK_MX) {  // a wave per chunk; lane i loads the descriptor of the wave's i-th
+                for (int j0 = 0; j0 < it.count; j0 += 256) {
+                    const int jl = j0 + wave + 4 * lane;
+                    MRChunk cl{};
+                    if (jl < it.count) cl = p.chunks[it.first + jl];
+                    for (int i = 0; j0 + wave + 4 * i < it.count && i < 64; ++i)
+                        mr_xpack_wave<STORE>(p, it.first + j0 + wave + 4 * i, lane_bcast(cl, i), 0, ar.x, ar.ldx, k,
+                                             lane);
+                }
             } else if (it.kind == BK_MV) {  // unit groups, X fragments shared through the LDS ring
                 for (int j = 0; j < it.count; ++j) mr_vunit_group<STORE, 1>(p, it.first + j, lds);
             } else if (it.kind == BK_MZ) {
                 float(*zs)[16] = reinterpret_cast<float(*)[16]>(lds) + wave * a.zs_rank;
-                for (int j = wave; j < it.count; j += 4) mr_zitem<STORE>(p, it.first + j, 0, lane, zs);
+                for (int j0 = 0; j0 < it.count; j0 += 256) {  // lane i: the wave's i-th item and its first member
+                    const int jl = j0 + wave + 4 * lane;
+                    MRZItem zl{};
+                    MRZMember ml{};
+                    if (jl < it.count) {
+                        zl = p.zitems[it.first + jl];
+                        ml = p.zmembers[zl.m0];
+                    }
+                    for (int i = 0; j0 + wave + 4 * i < it.count && i < 64; ++i)
+                        mr_zitem<STORE>(p, it.first + j0 + wave + 4 * i, lane_bcast(zl, i), lane_bcast(ml, i), 0, lane,
+                                        zs);
+                }
             } else {  // tile groups: the ring, then the chunk's step table
                 int2 *stab = reinterpret_cast<int2 *>(lds + 2 * MR<STORE>::BFRAG * 16);
                 for (int j = 0; j < it.count; ++j)

@@ -496,22 +496,33 @@ __device__ inline void mr_xpack(const DevPlanMR &p, int c, int nt, const float *
     }
 }
 
+// Lane i's copy of a descriptor held one per lane (i uniform), word by word.
+template <class T>
+__device__ inline T lane_bcast(const T &v, int i) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+    struct W { int w[sizeof(T) / 4]; };
+    W a = __builtin_bit_cast(W, v);
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(T) / 4); ++j) a.w[j] = __builtin_amdgcn_readlane(a.w[j], i);
+    return __builtin_bit_cast(T, a);
+}
+
 // ---------------------------------------------------------------------------
 // The same packing by one wave per (chunk, n-tile), for the batched kernel,
 // whose chunks are mostly a few hundred rows or less: the four waves of a
 // workgroup pack four chunks at once instead of one after the other. The
 // first 128 rows stay in registers between the maximum and the split; the rest
 // of a longer chunk is read a second time (from L2, as a rule). The fragments and the scale are the
-// ones mr_xpack and mr_xpack_tile write.
+// ones mr_xpack and mr_xpack_tile write. ch is chunk c's descriptor (row_begin, rows, nkb and xoff
+// are read), which the caller loads ahead.
 // ---------------------------------------------------------------------------
 template <int STORE>
-__device__ inline void mr_xpack_wave(const DevPlanMR &p, int c, int nt, const float *__restrict__ x, int64_t ldx,
-                                     int k, int lane) {
+__device__ inline void mr_xpack_wave(const DevPlanMR &p, int c, const MRChunk &ch, int nt,
+                                     const float *__restrict__ x, int64_t ldx, int k, int lane) {
     using F = MR<STORE>;
     constexpr int VW = F::VW;
     constexpr int KB = F::KB;
     constexpr int R = 128 / KB;  // K-blocks held in registers
-    const MRChunk ch = cload(p.chunks, c);
     const int n = nt * 16 + (lane & 15);
     const float *col = x + (int64_t)n * ldx + ch.row_begin;
     auto gather = [&](int kb, float (&v)[VW]) {  // zero past the chunk's rows and past column k
@@ -629,48 +640,48 @@ __device__ inline void mr_xpack_tile(const DevPlanMR &p, int c, int nt, const fl
 // Partial reduction and z packing, one wave per (z item, n-tile): the z of the
 // item's blocks stacked in their rows, then packed as B fragments with one
 // power-of-two scale for the item and n-tile. zs is the wave's LDS scratch of
-// kMaxRankMR x 16 floats.
+// kMaxRankMR x 16 floats; z is the item's descriptor and zm0 its first member's.
 // ---------------------------------------------------------------------------
 template <int STORE>
-__device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, float (*zs)[16]) {
+__device__ inline void mr_zitem(const DevPlanMR &p, int item, const MRZItem &z, const MRZMember &zm0, int nt,
+                                int lane, float (*zs)[16]) {
     using F = MR<STORE>;
     constexpr int VW = F::VW;
     constexpr int KB = F::KB;
-    const MRZItem z = cload(p.zitems, item);
     const int ncol = p.ntmax * 16;
     const int nn = lane & 15, g = lane >> 4;
     const int n = nt * 16 + nn;
     const int64_t ustride = (int64_t)64 * ncol;
     float amax = 0.0f;
-    // Columns j0 + step q (q < 4) of member zm, the loads of four columns and
-    // four units in flight (the addresses of columns past the rank are clamped,
+    // Columns j0 + step q (q < 8) of member zm, the loads of eight columns and
+    // two units in flight (the addresses of columns past the rank are clamped,
     // their sums dropped); each sum runs over the units in order.
     auto columns = [&](const MRZMember &zm, int j0, int step) {
-        const float *src[4];
+        const float *src[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int j = j0 + step * q < zm.rank ? j0 + step * q : zm.rank - 1;
             const int col = zm.vcol + j;
             src[q] = p.part + (zm.ubase + (int64_t)(col >> 6) * zm.nu) * ustride + (int64_t)(col & 63) * ncol + n;
         }
-        float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float a[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         int i0 = 0;
-        for (; i0 + 4 <= zm.nu; i0 += 4) {  // four units' loads, then their sums in order
-            float t[4][4];
+        for (; i0 + 2 <= zm.nu; i0 += 2) {  // two units' loads, then their sums in order
+            float t[2][8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) t[u][q] = src[q][(int64_t)(i0 + u) * ustride];
+                for (int q = 0; q < 8; ++q) t[u][q] = src[q][(int64_t)(i0 + u) * ustride];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] += t[u][q];
+                for (int q = 0; q < 8; ++q) a[q] += t[u][q];
         }
-        for (; i0 < zm.nu; ++i0)
+        if (i0 < zm.nu)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] += src[q][(int64_t)i0 * ustride];
+            for (int q = 0; q < 8; ++q) a[q] += src[q][(int64_t)i0 * ustride];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int j = j0 + step * q;
             if (j < zm.rank) {
                 float zsc = zm.scale;
@@ -682,12 +693,11 @@ __device__ inline void mr_zitem(const DevPlanMR &p, int item, int nt, int lane, 
         }
     };
     if (z.nmem == 1) {  // lane group g: columns g, g + 4, g + 8, ... of the block
-        const MRZMember zm = cload(p.zmembers, z.m0);
-        for (int j0 = g; j0 < zm.rank; j0 += 16) columns(zm, j0, 4);
-    } else {  // lane group g: blocks g, g + 4, ... of the item, four columns at a time
+        for (int j0 = g; j0 < zm0.rank; j0 += 32) columns(zm0, j0, 4);
+    } else {  // lane group g: blocks g, g + 4, ... of the item, eight columns at a time
         for (int mi = z.m0 + g; mi < z.m0 + z.nmem; mi += 4) {
             const MRZMember zm = p.zmembers[mi];
-            for (int j0 = 0; j0 < zm.rank; j0 += 4) columns(zm, j0, 1);
+            for (int j0 = 0; j0 < zm.rank; j0 += 8) columns(zm, j0, 1);
         }
     }
     amax = wave_max(amax);

@@ -69,7 +69,9 @@ __global__ __launch_bounds__(256) void k_zmfma(DevPlanMR p, int nt_used) {
     __shared__ float zs[4][kMaxRankMR][16];
     const int w = wave_id(4);
     if (w >= p.num_zitems * nt_used) return;
-    mr_zitem<STORE>(p, w / nt_used, w % nt_used, threadIdx.x & 63, zs[threadIdx.x >> 6]);
+    const MRZItem z = cload(p.zitems, w / nt_used);
+    const MRZMember zm0 = cload(p.zmembers, z.m0);
+    mr_zitem<STORE>(p, w / nt_used, z, zm0, w % nt_used, threadIdx.x & 63, zs[threadIdx.x >> 6]);
 }
 
 // LS: the chunks have at most 64 target-side segments, so a tile's step table
