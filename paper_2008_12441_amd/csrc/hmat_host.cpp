@@ -815,7 +815,8 @@ hmat_status build_plan_mr(const Tree &t, const Structure &st, const hmat_block_d
         // rows (so that a chunk of a few dozen rows still keeps the four waves of
         // a tile group busy), each a whole number of 16-row subtiles, at most 64;
         // a tile may hold rows of several target leaves
-        const int32_t th = std::min(64, ((m.rows + 4 * ((m.rows + 255) / 256) - 1) / (4 * ((m.rows + 255) / 256)) + 15) / 16 * 16);
+        const int32_t aim = 4 * ((m.rows + 255) / 256);  // tiles aimed at
+        const int32_t th = std::min(64, ((m.rows + aim - 1) / aim + 15) / 16 * 16);
         for (int32_t r0 = 0; r0 < m.rows; r0 += th) {
             hmat::MRTile tl{};
             tl.aoff = uf;
