@@ -296,19 +296,14 @@ hmat_status create_impl(const hmat_t *hs, int32_t count, const int32_t *nrhs, co
                 return set_error(HMAT_ERR_UNSUPPORTED, "member " + std::to_string(i) + ": more than 64 target-side segments per chunk");
             b->has_m = true;
             b->zs_rank = std::max(b->zs_rank, h->max_zrows);
-            const int32_t rows = h->mrp.max_chunk_rows;
-            if (rows <= 512)  // X packing through an LDS tile: 16 columns of a chunk, then four maxima
-                b->lds = std::max(b->lds, (size_t)(16 * (rows + 1) + 4) * 4);
             // group bodies: two B slots of one n-tile, then (target side) a chunk's step table
             const size_t ring = (size_t)2 * 16 * (h->storage == HMAT_STORE_FP32 ? 64 : 128);
             b->lds = std::max(b->lds, ring + (size_t)8 * h->mrp.max_nsteps);
         }
     }
     b->zs_rank = (b->zs_rank + 3) / 4 * 4;
-    if (b->has_m) {
-        b->lds = std::max(b->lds, (size_t)4 * 4);                    // X packing: one maximum per wave
-        b->lds = std::max(b->lds, (size_t)4 * b->zs_rank * 16 * 4);  // z packing: rank x 16 values per wave
-    }
+    if (b->has_m)  // z packing: rank x 16 values per wave (X packing takes no LDS: a wave per chunk)
+        b->lds = std::max(b->lds, (size_t)4 * b->zs_rank * 16 * 4);
     b->lds = std::max<size_t>((b->lds + 15) / 16 * 16, 16);
     // take the references now: release_batch drops one per member
     for (int32_t i = 0; i < count; ++i) {
